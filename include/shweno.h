@@ -1,0 +1,156 @@
+/*
+ * shweno.h -- C ABI of the MI355X (gfx950) ADER-SHWENO library.
+ *
+ * The library advances one or many independent problems
+ *     W_t + F(W)_x (+ G(W)_y) = 0,   W(x, 0) = W0(x)
+ * on uniform Cartesian meshes with the one-stage ADER-SHWENO scheme of Luo,
+ * Li, Qiu, Zhu and Chen (arXiv 2304.09724): the problem statement is sec. 2
+ * eq. (1) and sec. 3 eq. (2); the state carried from step to step is the cell
+ * averages W and the cell averages of the derivatives V = avg W_x (sec. 2.4,
+ * eq. (vv)) and, in 2D, Y = avg W_y and Z = avg W_xy (sec. 3.2); one step is
+ * the algorithm of sec. 4 (Steps 1-5).
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns a shw_status; nothing throws across the ABI.
+ *  - Argument errors return SHW_EINVAL before any device work is queued.
+ *  - Device memory for the state and the workspace is owned by the caller
+ *    (allocated by any means, e.g. PyTorch); the library never frees it.  The
+ *    library owns only the context object and what it allocates itself for
+ *    the learned gate.
+ *  - All device work is queued on the HIP stream given at creation, in
+ *    order; calls documented as "synchronising" wait for that stream.
+ *  - One context per stream; calls on one context are not re-entrant.
+ *  - Non-physical states (a non-finite value, rho <= 0 or p <= 0 in a cell
+ *    average) are detected on the device, are sticky per instance, and are
+ *    reported as SHW_ENONPHYS by the next synchronising call; that instance
+ *    stops advancing, the others continue.  shw_status_detail names it.
+ *
+ * State layout (one instance): planes [q][m][ny][nx] of doubles, x fastest;
+ * q = 0 W, 1 V, (2D:) 2 Y, 3 Z; m conservative components (rho, rho u
+ * [, rho v], E) for Euler, one for scalar equations.  Derivative averages
+ * are in physical units.  A batch is the instances' blocks back to back, in
+ * the order of the mesh array.
+ */
+#ifndef SHWENO_H
+#define SHWENO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SHW_OK = 0,
+    SHW_EINVAL = -1,     /* invalid argument (nothing was queued) */
+    SHW_ENOMEM = -2,     /* host allocation failed */
+    SHW_EDEVICE = -3,    /* a HIP call failed */
+    SHW_ENONPHYS = -4,   /* a non-physical state was detected */
+    SHW_ESTATE = -5      /* call made in the wrong state (e.g. gate not loaded) */
+} shw_status;
+
+enum { SHW_ADVECTION = 0, SHW_BURGERS = 1, SHW_EULER = 2 };
+enum { SHW_BC_PERIODIC = 0, SHW_BC_TRANSMISSIVE = 1, SHW_BC_REFLECTIVE = 2 };
+enum { SHW_W_NONLINEAR = 0, SHW_W_LINEAR = 1, SHW_W_GATED = 2 };
+
+/* One uniform mesh (sec. 2: cells I_j of width dx; sec. 3: cells I_ij).
+ * dim 1: nx cells on [x0, x1], ny must be 1.  dim 2: nx x ny cells.
+ * bc: x-low, x-high, y-low, y-high (SHW_BC_*); the two ends of a periodic
+ * direction must both be periodic.  1D needs nx >= 3, 2D nx, ny >= 3. */
+typedef struct {
+    int dim;
+    int nx, ny;
+    double x0, x1, y0, y1;
+    int bc[4];
+} shw_mesh;
+
+/* Scheme parameters.  eq: SHW_*; gamma: ratio of specific heats (Euler,
+ * sec. 5 uses 1.4); adv_a, adv_b: advection speeds; cfl: Courant number for
+ * the device-computed step (sec. 5 uses 0.9); eps: regulariser of the
+ * nonlinear weights; lin_w: linear weights of the big stencil and the two
+ * small ones (sec. 2.3: 0.994, 0.003, 0.003); charwise: Euler only,
+ * reconstruct characteristic fields; weights: SHW_W_*; gate_threshold: gated
+ * mode, cells whose gate score is >= threshold take the full nonlinear
+ * reconstruction. */
+typedef struct {
+    int eq;
+    int charwise;
+    int weights;
+    double gamma;
+    double adv_a, adv_b;
+    double cfl;
+    double eps;
+    double lin_w[3];
+    double gate_threshold;
+} shw_params;
+
+typedef struct shw_ctx shw_ctx;
+
+/* Number of doubles of one instance's state (q * m * nx * ny), 0 if the mesh
+ * or parameters are invalid. */
+size_t shw_state_doubles(const shw_mesh *mesh, const shw_params *params);
+
+/* Bytes of device workspace shw_create needs for this batch, 0 if invalid. */
+size_t shw_workspace_bytes(const shw_mesh *meshes, int n_inst, const shw_params *params);
+
+/* Create a context for n_inst instances (all with the same dim and params).
+ * d_state: device buffer of sum(shw_state_doubles) doubles, the current
+ * state (caller-owned; it holds the current state after every call).
+ * d_workspace: device buffer of shw_workspace_bytes bytes (caller-owned,
+ * contents irrelevant).  hip_stream: a hipStream_t (NULL = default).  Times
+ * start at 0.  Synchronising. */
+shw_status shw_create(const shw_mesh *meshes, int n_inst, const shw_params *params,
+                      double *d_state, void *d_workspace, void *hip_stream,
+                      shw_ctx **out);
+
+/* Release the context (never the caller's buffers).  Safe on NULL. */
+void shw_destroy(shw_ctx *ctx);
+
+/* Copy one instance's state in (set) or out (get), layout as above.
+ * src/dst on the device if *_on_device is non-zero, else in host memory
+ * (then the call is synchronising).  Setting a state clears that
+ * instance's non-physical flag. */
+shw_status shw_set_state(shw_ctx *ctx, int inst, const double *src, int src_on_device);
+shw_status shw_get_state(shw_ctx *ctx, int inst, double *dst, int dst_on_device);
+
+/* Per-instance simulated time and step count (host arrays of n_inst);
+ * either pointer may be NULL.  Synchronising.  shw_set_time sets t. */
+shw_status shw_get_time(shw_ctx *ctx, double *t, long long *steps);
+shw_status shw_set_time(shw_ctx *ctx, const double *t);
+
+/* Step size from the CFL condition for every instance (host array of
+ * n_inst): 1D dt = cfl dx / max_j(|u|+c); 2D dt = cfl / max_ij((|u|+c)/dx +
+ * (|v|+c)/dy); scalar equations use |a| (advection) or |W| (Burgers).
+ * Synchronising. */
+shw_status shw_compute_dt(shw_ctx *ctx, double *dt);
+
+/* One time step of every instance with the given step sizes (host array of
+ * n_inst; entries <= 0 leave that instance alone).  Asynchronous. */
+shw_status shw_step(shw_ctx *ctx, const double *dt);
+
+/* Advance every instance i to time T[i] (host array) with device-computed CFL
+ * steps, the last step of each instance clamped to end exactly at T[i];
+ * at most max_steps steps per instance in this call.  Writes the number of
+ * steps taken by each instance to steps_out (host array, may be NULL).
+ * Synchronising; returns SHW_ENONPHYS if any instance went non-physical. */
+shw_status shw_advance_to(shw_ctx *ctx, const double *T, long long max_steps,
+                          long long *steps_out);
+
+/* Per-cell gate flags for SHW_W_GATED (one byte per cell, non-zero = full
+ * nonlinear reconstruction, zero = linear weights), for instance inst, from
+ * host memory.  Overrides any flags computed by the learned gate until the
+ * gate is evaluated again. */
+shw_status shw_set_flags(shw_ctx *ctx, int inst, const uint8_t *flags);
+
+/* First failing instance and a message for the last error (any may be
+ * NULL). */
+shw_status shw_status_detail(shw_ctx *ctx, int *bad_instance, char *msg, size_t msg_len);
+
+/* Library version string. */
+const char *shw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,194 @@
+"""MI355X (gfx950) ADER-SHWENO library: Python binding of the C ABI in
+include/shweno.h.
+
+This module only marshals arguments: every step of the scheme runs in the HIP
+kernels of libshweno.so.  PyTorch provides the device memory (state and
+workspace tensors) and the stream.  Loading fails loudly when the library is
+not built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libshweno.so")
+
+ADVECTION, BURGERS, EULER = 0, 1, 2
+BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE = 0, 1, 2
+W_NONLINEAR, W_LINEAR, W_GATED = 0, 1, 2
+STATUS = {0: "SHW_OK", -1: "SHW_EINVAL", -2: "SHW_ENOMEM", -3: "SHW_EDEVICE",
+          -4: "SHW_ENONPHYS", -5: "SHW_ESTATE"}
+
+
+class ShwError(RuntimeError):
+    def __init__(self, code, msg="", bad_instance=-1):
+        super().__init__(f"{STATUS.get(code, code)}: {msg} (instance {bad_instance})")
+        self.code = code
+        self.bad_instance = bad_instance
+
+
+class Mesh(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("x0", ctypes.c_double), ("x1", ctypes.c_double),
+                ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+                ("bc", ctypes.c_int * 4)]
+
+    @classmethod
+    def line(cls, n, x0, x1, bc=BC_PERIODIC):
+        return cls(1, n, 1, x0, x1, 0.0, 1.0, (ctypes.c_int * 4)(bc, bc, bc, bc))
+
+    @classmethod
+    def rect(cls, nx, ny, x0, x1, y0, y1, bcx=BC_PERIODIC, bcy=BC_PERIODIC):
+        return cls(2, nx, ny, x0, x1, y0, y1, (ctypes.c_int * 4)(bcx, bcx, bcy, bcy))
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("eq", ctypes.c_int), ("charwise", ctypes.c_int), ("weights", ctypes.c_int),
+                ("gamma", ctypes.c_double), ("adv_a", ctypes.c_double),
+                ("adv_b", ctypes.c_double), ("cfl", ctypes.c_double), ("eps", ctypes.c_double),
+                ("lin_w", ctypes.c_double * 3), ("gate_threshold", ctypes.c_double)]
+
+    @classmethod
+    def make(cls, eq=EULER, charwise=True, weights=W_NONLINEAR, gamma=1.4, adv_a=1.0,
+             adv_b=0.0, cfl=0.9, eps=1e-6, lin_w=(0.994, 0.003, 0.003), gate_threshold=0.5):
+        return cls(eq, int(charwise), weights, gamma, adv_a, adv_b, cfl, eps,
+                   (ctypes.c_double * 3)(*lin_w), gate_threshold)
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_LL = ctypes.POINTER(ctypes.c_longlong)
+
+
+def lib():
+    """Load libshweno.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run python -m paper_2304_09724_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        MP, PP = ctypes.POINTER(Mesh), ctypes.POINTER(Params)
+        vp = ctypes.c_void_p
+        L.shw_version.restype = ctypes.c_char_p
+        L.shw_state_doubles.argtypes = [MP, PP]
+        L.shw_state_doubles.restype = ctypes.c_size_t
+        L.shw_workspace_bytes.argtypes = [MP, ctypes.c_int, PP]
+        L.shw_workspace_bytes.restype = ctypes.c_size_t
+        L.shw_create.argtypes = [MP, ctypes.c_int, PP, vp, vp, vp, ctypes.POINTER(vp)]
+        L.shw_destroy.argtypes = [vp]
+        L.shw_destroy.restype = None
+        L.shw_set_state.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
+        L.shw_get_state.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int]
+        L.shw_get_time.argtypes = [vp, _D, _LL]
+        L.shw_set_time.argtypes = [vp, _D]
+        L.shw_compute_dt.argtypes = [vp, _D]
+        L.shw_step.argtypes = [vp, _D]
+        L.shw_advance_to.argtypes = [vp, _D, ctypes.c_longlong, _LL]
+        L.shw_set_flags.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8)]
+        L.shw_status_detail.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_char_p,
+                                        ctypes.c_size_t]
+        _lib = L
+    return _lib
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_D)
+
+
+class Solver:
+    """A batch of instances on one GPU.  meshes: list of Mesh (same dim);
+    params: Params.  State and workspace are torch tensors on `device`."""
+
+    def __init__(self, meshes, params: Params, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        L = lib()
+        self.meshes = list(meshes)
+        self.params = params
+        self.n = len(self.meshes)
+        arr = (Mesh * self.n)(*self.meshes)
+        self._marr = arr
+        self.sizes = [L.shw_state_doubles(ctypes.byref(m), ctypes.byref(params)) for m in self.meshes]
+        if any(s == 0 for s in self.sizes):
+            raise ShwError(-1, "invalid mesh or parameters")
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        ws = L.shw_workspace_bytes(arr, self.n, ctypes.byref(params))
+        if ws == 0:
+            raise ShwError(-1, "invalid batch")
+        self.device = torch.device(device)
+        self.state = torch.zeros(int(self.offsets[-1]), dtype=torch.float64, device=self.device)
+        self.workspace = torch.empty(ws, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        self._check(L.shw_create(arr, self.n, ctypes.byref(params),
+                                 ctypes.c_void_p(self.state.data_ptr()),
+                                 ctypes.c_void_p(self.workspace.data_ptr()),
+                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx)),
+                    ctx=None)
+        self.ctx = ctx
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx and _lib is not None:
+            _lib.shw_destroy(ctx)
+            self.ctx = None
+
+    def _check(self, code, ctx="self"):
+        if code == 0:
+            return
+        c = self.ctx if ctx == "self" else None
+        bad, msg = ctypes.c_int(-1), ctypes.create_string_buffer(256)
+        if c:
+            lib().shw_status_detail(c, ctypes.byref(bad), msg, 256)
+        raise ShwError(code, msg.value.decode(), bad.value)
+
+    def shape(self, i):
+        m = self.meshes[i]
+        q = 2 if m.dim == 1 else 4
+        comps = {ADVECTION: 1, BURGERS: 1, EULER: 3 if m.dim == 1 else 4}[self.params.eq]
+        return (q, comps, m.nx) if m.dim == 1 else (q, comps, m.ny, m.nx)
+
+    def set_state(self, i, arr):
+        a = np.ascontiguousarray(np.asarray(arr, dtype=np.float64).reshape(self.shape(i)))
+        self._check(lib().shw_set_state(self.ctx, i, a.ctypes.data_as(ctypes.c_void_p), 0))
+
+    def get_state(self, i) -> np.ndarray:
+        a = np.empty(self.shape(i))
+        self._check(lib().shw_get_state(self.ctx, i, a.ctypes.data_as(ctypes.c_void_p), 0))
+        return a
+
+    def state_view(self, i):
+        """Device tensor view of instance i's state (no copy)."""
+        return self.state[int(self.offsets[i]):int(self.offsets[i + 1])].view(self.shape(i))
+
+    def times(self):
+        t = np.zeros(self.n)
+        s = np.zeros(self.n, dtype=np.int64)
+        self._check(lib().shw_get_time(self.ctx, _dptr(t), s.ctypes.data_as(_LL)))
+        return t, s
+
+    def set_times(self, t):
+        t = np.ascontiguousarray(np.broadcast_to(np.asarray(t, float), (self.n,)))
+        self._check(lib().shw_set_time(self.ctx, _dptr(t)))
+
+    def compute_dt(self):
+        dt = np.zeros(self.n)
+        self._check(lib().shw_compute_dt(self.ctx, _dptr(dt)))
+        return dt
+
+    def step(self, dt):
+        dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, float), (self.n,)))
+        self._check(lib().shw_step(self.ctx, _dptr(dt)))
+
+    def advance_to(self, T, max_steps=1_000_000):
+        T = np.ascontiguousarray(np.broadcast_to(np.asarray(T, float), (self.n,)))
+        steps = np.zeros(self.n, dtype=np.int64)
+        self._check(lib().shw_advance_to(self.ctx, _dptr(T), max_steps, steps.ctypes.data_as(_LL)))
+        return steps
+
+    def set_flags(self, i, flags):
+        f = np.ascontiguousarray(np.asarray(flags, dtype=np.uint8).reshape(-1))
+        self._check(lib().shw_set_flags(self.ctx, i, f.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))))

@@ -1,0 +1,257 @@
+// shw_math.h -- device arithmetic of the ADER-SHWENO step for gfx950.
+//
+// Closed forms used by the sweep kernels.  Each function names the part of
+// the paper (arXiv 2304.09724) it computes; the derivations are restated in
+// the comments, so a reader can check them against the paper by hand.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace shw {
+
+enum { ADV = 0, BURG = 1, EULER = 2 };
+enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
+enum { W_NONLINEAR = 0, W_LINEAR = 1, W_GATED = 2 };
+
+// Scheme parameters as the kernels see them.
+struct DevParams {
+    double gamma;
+    double adv_a, adv_b;
+    double cfl;
+    double eps;
+    double g1, g2, g3;   // linear weights: big quartic, left linear, right linear
+    int charwise;
+    int weights;
+};
+
+template <int EQ, int DIM>
+struct NComp { static constexpr int M = (EQ == EULER) ? (DIM == 1 ? 3 : 4) : 1; };
+
+// 4-point Gauss-Lobatto on [-1/2, 1/2] (time rule of eq. (flux) per Remark 2,
+// and the edge rule of eq. (fx2d)): nodes -1/2, -h, h, 1/2 with h = 1/(2 sqrt5),
+// weights 1/12, 5/12, 5/12, 1/12.
+constexpr double LOB_H = 0.22360679774997896964;
+constexpr double LOB_W0 = 1.0 / 12.0;
+constexpr double LOB_W1 = 5.0 / 12.0;
+
+// ---------------------------------------------------------------------------
+// SHWENO reconstruction of one scalar field on one cell (sec. 2.3).
+// xi = (x - x_j)/dx.  Data: averages am, a0, ap of cells j-1, j, j+1 and the
+// scaled derivative averages bm = dx V_{j-1}, bp = dx V_{j+1}.
+// ---------------------------------------------------------------------------
+
+// Quartic whose averages over cells -1, 0, 1 and whose increments
+// p(l+1/2) - p(l-1/2) over cells -1, +1 match the data (solved by hand from
+// those five linear conditions).
+__device__ __forceinline__ void big_quartic(double am, double a0, double ap,
+                                            double bm, double bp, double c[5])
+{
+    const double s = am + ap, d = ap - am, bs = bm + bp, bd = bp - bm;
+    c[0] = (1148.0 * a0 - 94.0 * s + 27.0 * bd) * (1.0 / 960.0);
+    c[1] = (13.0 * d - 5.0 * bs) * (1.0 / 16.0);
+    c[2] = (10.0 * s - 20.0 * a0 - 3.0 * bd) * (1.0 / 8.0);
+    c[3] = (bs - d) * 0.25;
+    c[4] = (4.0 * a0 - 2.0 * s + bd) * 0.25;
+}
+
+// Nonlinear weights of the three candidates (big quartic, left linear a0 +
+// (a0-am) xi, right linear a0 + (ap-a0) xi).  Smoothness indicators are
+// sum_k int (d^k p/dxi^k)^2 over the cell; for the quartic that integral is
+// the quadratic form below (exact integration of the squared derivatives).
+// Simple-WENO weights: tau = ((|b1-b2| + |b1-b3|)/2)^2,
+// w_l ~ g_l (1 + tau/(b_l + eps)).
+__device__ __forceinline__ void nonlinear_weights(const double c[5], double am, double a0,
+                                                  double ap, const DevParams &P,
+                                                  double w[3])
+{
+    const double b1 = c[1] * c[1] + 0.5 * c[1] * c[3] + (13.0 / 3.0) * c[2] * c[2]
+                    + (21.0 / 5.0) * c[2] * c[4] + (3129.0 / 80.0) * c[3] * c[3]
+                    + (87617.0 / 140.0) * c[4] * c[4];
+    const double dl = a0 - am, dr = ap - a0;
+    const double b2 = dl * dl, b3 = dr * dr;
+    double tau = 0.5 * (fabs(b1 - b2) + fabs(b1 - b3));
+    tau = tau * tau;
+    const double w1 = P.g1 * (1.0 + tau / (b1 + P.eps));
+    const double w2 = P.g2 * (1.0 + tau / (b2 + P.eps));
+    const double w3 = P.g3 * (1.0 + tau / (b3 + P.eps));
+    const double inv = 1.0 / (w1 + w2 + w3);
+    w[0] = w1 * inv;
+    w[1] = w2 * inv;
+    w[2] = w3 * inv;
+}
+
+// Final polynomial (w1/g1)(p1 - g2 p2 - g3 p3) + w2 p2 + w3 p3 in place of the
+// quartic coefficients c (the linear candidates only touch xi^0 and xi^1).
+__device__ __forceinline__ void combine(double c[5], double am, double a0, double ap,
+                                        const double w[3], const DevParams &P)
+{
+    const double f = w[0] / P.g1;
+    const double dl = a0 - am, dr = ap - a0;
+    c[0] = f * (c[0] - (P.g2 + P.g3) * a0) + (w[1] + w[2]) * a0;
+    c[1] = f * (c[1] - P.g2 * dl - P.g3 * dr) + w[1] * dl + w[2] * dr;
+    c[2] *= f;
+    c[3] *= f;
+    c[4] *= f;
+}
+
+// d^k p/dxi^k at xi = -1/2 (lo) and xi = +1/2 (hi), k = 0..4.
+__device__ __forceinline__ void edge_derivs(const double c[5], double lo[5], double hi[5])
+{
+    const double e0 = c[0] + 0.25 * c[2] + 0.0625 * c[4], o0 = 0.5 * c[1] + 0.125 * c[3];
+    const double e1 = c[1] + 0.75 * c[3], o1 = c[2] + 0.5 * c[4];
+    const double e2 = 2.0 * c[2] + 3.0 * c[4], o2 = 3.0 * c[3];
+    const double e3 = 6.0 * c[3], o3 = 12.0 * c[4];
+    hi[0] = e0 + o0; lo[0] = e0 - o0;
+    hi[1] = e1 + o1; lo[1] = e1 - o1;
+    hi[2] = e2 + o2; lo[2] = e2 - o2;
+    hi[3] = e3 + o3; lo[3] = e3 - o3;
+    hi[4] = 24.0 * c[4]; lo[4] = 24.0 * c[4];
+}
+
+// ---------------------------------------------------------------------------
+// Euler equations (sec. 5, eqs. (Euler) and (2d)): E = p/(g-1) + rho|u|^2/2.
+// ---------------------------------------------------------------------------
+
+template <int DIM>
+__device__ __forceinline__ double pressure(const double *W, double gamma)
+{
+    if constexpr (DIM == 1) {
+        return (gamma - 1.0) * (W[2] - 0.5 * W[1] * W[1] / W[0]);
+    } else {
+        return (gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
+    }
+}
+
+// Eigenvectors of the flux Jacobian in direction DIR (0 = x, 1 = y) at W.
+// R has the right eigenvectors as columns (speeds un-c, un, [un,] un+c), L =
+// R^{-1} in closed form, with b1 = (g-1)/c^2 and b2 = b1 |u|^2 / 2.
+template <int DIM, int DIR>
+__device__ __forceinline__ void euler_eigen(const double *W, double gamma,
+                                            double R[][NComp<EULER, DIM>::M],
+                                            double L[][NComp<EULER, DIM>::M],
+                                            double lam[NComp<EULER, DIM>::M])
+{
+    const double ir = 1.0 / W[0];
+    const double u = W[1] * ir;
+    if constexpr (DIM == 1) {
+        const double p = (gamma - 1.0) * (W[2] - 0.5 * W[1] * u);
+        const double c2 = gamma * p * ir;
+        const double c = sqrt(c2), ic = 1.0 / c;
+        const double H = (W[2] + p) * ir;
+        const double b1 = (gamma - 1.0) / c2, b2 = 0.5 * b1 * u * u;
+        R[0][0] = 1.0;       R[0][1] = 1.0;         R[0][2] = 1.0;
+        R[1][0] = u - c;     R[1][1] = u;           R[1][2] = u + c;
+        R[2][0] = H - u * c; R[2][1] = 0.5 * u * u; R[2][2] = H + u * c;
+        L[0][0] = 0.5 * (b2 + u * ic); L[0][1] = -0.5 * (b1 * u + ic); L[0][2] = 0.5 * b1;
+        L[1][0] = 1.0 - b2;            L[1][1] = b1 * u;               L[1][2] = -b1;
+        L[2][0] = 0.5 * (b2 - u * ic); L[2][1] = -0.5 * (b1 * u - ic); L[2][2] = 0.5 * b1;
+        lam[0] = u - c; lam[1] = u; lam[2] = u + c;
+    } else {
+        const double v = W[2] * ir;
+        const double q2 = u * u + v * v;
+        const double p = (gamma - 1.0) * (W[3] - 0.5 * W[0] * q2);
+        const double c2 = gamma * p * ir;
+        const double c = sqrt(c2), ic = 1.0 / c;
+        const double H = (W[3] + p) * ir;
+        const double b1 = (gamma - 1.0) / c2, b2 = 0.5 * b1 * q2;
+        // normal (n) and tangential (s) velocity and momentum slots
+        const double un = DIR == 0 ? u : v, us = DIR == 0 ? v : u;
+        constexpr int N = DIR == 0 ? 1 : 2, T = DIR == 0 ? 2 : 1;
+        R[0][0] = 1.0; R[0][1] = 1.0; R[0][2] = 0.0; R[0][3] = 1.0;
+        R[N][0] = un - c; R[N][1] = un; R[N][2] = 0.0; R[N][3] = un + c;
+        R[T][0] = us; R[T][1] = us; R[T][2] = 1.0; R[T][3] = us;
+        R[3][0] = H - un * c; R[3][1] = 0.5 * q2; R[3][2] = us; R[3][3] = H + un * c;
+        L[0][0] = 0.5 * (b2 + un * ic); L[0][N] = -0.5 * (b1 * un + ic);
+        L[0][T] = -0.5 * b1 * us;       L[0][3] = 0.5 * b1;
+        L[1][0] = 1.0 - b2; L[1][N] = b1 * un; L[1][T] = b1 * us; L[1][3] = -b1;
+        L[2][0] = -us; L[2][N] = 0.0; L[2][T] = 1.0; L[2][3] = 0.0;
+        L[3][0] = 0.5 * (b2 - un * ic); L[3][N] = -0.5 * (b1 * un - ic);
+        L[3][T] = -0.5 * b1 * us;       L[3][3] = 0.5 * b1;
+        lam[0] = un - c; lam[1] = un; lam[2] = un; lam[3] = un + c;
+    }
+}
+
+// Physical flux in x of a point state (scalar equations: a W or W^2/2).
+template <int EQ, int DIM>
+__device__ __forceinline__ void phys_flux_x(const double *W, const DevParams &P, double *F)
+{
+    if constexpr (EQ == ADV) {
+        F[0] = P.adv_a * W[0];
+    } else if constexpr (EQ == BURG) {
+        F[0] = 0.5 * W[0] * W[0];
+    } else if constexpr (DIM == 1) {
+        const double u = W[1] / W[0];
+        const double p = (P.gamma - 1.0) * (W[2] - 0.5 * W[1] * u);
+        F[0] = W[1];
+        F[1] = W[1] * u + p;
+        F[2] = (W[2] + p) * u;
+    } else {
+        const double ir = 1.0 / W[0];
+        const double u = W[1] * ir;
+        const double p = (P.gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) * ir);
+        F[0] = W[1];
+        F[1] = W[1] * u + p;
+        F[2] = W[2] * u;
+        F[3] = (W[3] + p) * u;
+    }
+}
+
+// HLLC Godunov state at x/t = 0 (leading term, sec. 2.1.1), Davis wave-speed
+// estimates, contact speed from the HLLC jump conditions; a state on a
+// boundary between two branches goes to the left one.
+template <int DIM>
+__device__ __forceinline__ void hllc_state(const double *WL, const double *WR,
+                                           double gamma, double *Ws)
+{
+    constexpr int M = NComp<EULER, DIM>::M;
+    const double rl = WL[0], rr = WR[0];
+    const double irl = 1.0 / rl, irr = 1.0 / rr;
+    const double ul = WL[1] * irl, ur = WR[1] * irr;
+    const double pl = pressure<DIM>(WL, gamma), pr = pressure<DIM>(WR, gamma);
+    const double cl = sqrt(gamma * pl * irl), cr = sqrt(gamma * pr * irr);
+    const double SL = fmin(ul - cl, ur - cr);
+    const double SR = fmax(ul + cl, ur + cr);
+    const double ml = rl * (SL - ul), mr = rr * (SR - ur);
+    const double Ss = (pr - pl + ul * ml - ur * mr) / (ml - mr);
+    if (0.0 <= SL) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) Ws[c] = WL[c];
+        return;
+    }
+    if (0.0 > SR) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) Ws[c] = WR[c];
+        return;
+    }
+    const bool left = 0.0 <= Ss;
+    const double *WK = left ? WL : WR;
+    const double rk = left ? rl : rr, uk = left ? ul : ur, pk = left ? pl : pr;
+    const double SK = left ? SL : SR, mk = left ? ml : mr;
+    const double f = mk / (SK - Ss);
+    Ws[0] = f;
+    Ws[1] = f * Ss;
+    if constexpr (DIM == 2) Ws[2] = f * (WK[2] / rk);
+    Ws[M - 1] = f * (WK[M - 1] / rk + (Ss - uk) * (Ss + pk / mk));
+}
+
+// Upwind solution at x/t = 0 of a linear Riemann problem with speed lam; a
+// speed below 1e-10 of the system's fastest speed counts as zero and takes
+// the mean (a rounding-level speed must not pick a side).
+__device__ __forceinline__ double upwind(double lam, double scale, double l, double r)
+{
+    const double z = 1e-10 * scale;
+    return lam > z ? l : (lam < -z ? r : 0.5 * (l + r));
+}
+
+// Exact Godunov state of Burgers' equation at x/t = 0 (sec. 2.1.1, scalar case).
+__device__ __forceinline__ double burgers_state(double ul, double ur)
+{
+    if (ul > ur) {
+        const double s = 0.5 * (ul + ur);
+        return s > 0.0 ? ul : (s < 0.0 ? ur : s);
+    }
+    return ul >= 0.0 ? ul : (ur <= 0.0 ? ur : 0.0);
+}
+
+} // namespace shw

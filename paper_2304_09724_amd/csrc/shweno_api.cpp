@@ -1,0 +1,392 @@
+// shweno_api.cpp -- host side of the C ABI declared in include/shweno.h:
+// argument checking, the device workspace layout, launches and error
+// reporting.  All arithmetic of the scheme runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/shweno.h"
+#include "shw_kernels.h"
+
+using namespace shw;
+
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int ncomp(int eq, int dim) { return eq == SHW_EULER ? (dim == 1 ? 3 : 4) : 1; }
+
+bool valid_params(const shw_params *p)
+{
+    if (!p) return false;
+    if (p->eq < SHW_ADVECTION || p->eq > SHW_EULER) return false;
+    if (p->weights < SHW_W_NONLINEAR || p->weights > SHW_W_GATED) return false;
+    if (p->eq == SHW_EULER && !(p->gamma > 1.0)) return false;
+    if (!(p->cfl > 0.0) || !(p->eps > 0.0)) return false;
+    for (int k = 0; k < 3; ++k)
+        if (!(p->lin_w[k] > 0.0)) return false;
+    if (std::fabs(p->lin_w[0] + p->lin_w[1] + p->lin_w[2] - 1.0) > 1e-12) return false;
+    return true;
+}
+
+bool valid_mesh(const shw_mesh *m)
+{
+    if (!m) return false;
+    if (m->dim != 1 && m->dim != 2) return false;
+    if (m->nx < 3 || !(m->x1 > m->x0)) return false;
+    if (m->dim == 1 && m->ny != 1) return false;
+    if (m->dim == 2 && (m->ny < 3 || !(m->y1 > m->y0))) return false;
+    for (int k = 0; k < (m->dim == 1 ? 2 : 4); ++k)
+        if (m->bc[k] < SHW_BC_PERIODIC || m->bc[k] > SHW_BC_REFLECTIVE) return false;
+    if ((m->bc[0] == SHW_BC_PERIODIC) != (m->bc[1] == SHW_BC_PERIODIC)) return false;
+    if (m->dim == 2 && (m->bc[2] == SHW_BC_PERIODIC) != (m->bc[3] == SHW_BC_PERIODIC))
+        return false;
+    return true;
+}
+
+size_t state_doubles(const shw_mesh *m, int eq)
+{
+    return (size_t)(m->dim == 1 ? 2 : 4) * ncomp(eq, m->dim) * (size_t)m->nx * m->ny;
+}
+
+// Device workspace carved out of the caller's buffer.
+struct Layout {
+    size_t alt = 0, inst = 0, order = 0, queue = 0, ist = 0, t_end = 0, dt = 0,
+           flags = 0, total = 0;
+};
+
+Layout make_layout(const shw_mesh *meshes, int n_inst, const shw_params *p)
+{
+    Layout L;
+    size_t state = 0, cells = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        state += state_doubles(&meshes[i], p->eq);
+        cells += (size_t)meshes[i].nx * meshes[i].ny;
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t at = off; off = align_up(off + bytes, 256); return at; };
+    L.alt = take(state * sizeof(double));
+    L.inst = take((size_t)n_inst * std::max(sizeof(Inst1D), sizeof(Inst2D)));
+    L.order = take((size_t)n_inst * sizeof(int));
+    L.queue = take(256);
+    L.ist = take((size_t)n_inst * sizeof(InstState));
+    L.t_end = take((size_t)n_inst * sizeof(double));
+    L.dt = take((size_t)n_inst * sizeof(double));
+    L.flags = take(cells);
+    L.total = off;
+    return L;
+}
+
+} // namespace
+
+struct shw_ctx {
+    int n_inst = 0, dim = 1, m = 1;
+    shw_params params{};
+    DevParams dp{};
+    std::vector<shw_mesh> meshes;
+    std::vector<long long> off, cell_off;
+    double *state = nullptr;
+    char *ws = nullptr;
+    Layout lay;
+    hipStream_t stream = nullptr;
+    int grid1d = 1;
+    int bad_instance = -1;
+    std::string msg;
+
+    template <class T> T *at(size_t o) { return reinterpret_cast<T *>(ws + o); }
+    double *alt() { return at<double>(lay.alt); }
+    InstState *ist() { return at<InstState>(lay.ist); }
+
+    shw_status fail(shw_status s, const std::string &m_) { msg = m_; return s; }
+    shw_status hip(hipError_t e, const char *what)
+    {
+        if (e == hipSuccess) return SHW_OK;
+        msg = std::string(what) + ": " + hipGetErrorString(e);
+        return SHW_EDEVICE;
+    }
+};
+
+extern "C" {
+
+const char *shw_version(void) { return "shweno-gfx950 0.1"; }
+
+size_t shw_state_doubles(const shw_mesh *mesh, const shw_params *params)
+{
+    if (!valid_mesh(mesh) || !valid_params(params)) return 0;
+    return state_doubles(mesh, params->eq);
+}
+
+size_t shw_workspace_bytes(const shw_mesh *meshes, int n_inst, const shw_params *params)
+{
+    if (!meshes || n_inst < 1 || !valid_params(params)) return 0;
+    for (int i = 0; i < n_inst; ++i)
+        if (!valid_mesh(&meshes[i]) || meshes[i].dim != meshes[0].dim) return 0;
+    return make_layout(meshes, n_inst, params).total;
+}
+
+shw_status shw_create(const shw_mesh *meshes, int n_inst, const shw_params *params,
+                      double *d_state, void *d_workspace, void *hip_stream, shw_ctx **out)
+{
+    if (!out) return SHW_EINVAL;
+    *out = nullptr;
+    if (!meshes || n_inst < 1 || !valid_params(params) || !d_state || !d_workspace)
+        return SHW_EINVAL;
+    for (int i = 0; i < n_inst; ++i)
+        if (!valid_mesh(&meshes[i]) || meshes[i].dim != meshes[0].dim) return SHW_EINVAL;
+    if (params->eq == SHW_BURGERS && meshes[0].dim != 1) return SHW_EINVAL;
+    shw_ctx *c = new (std::nothrow) shw_ctx;
+    if (!c) return SHW_ENOMEM;
+    c->n_inst = n_inst;
+    c->dim = meshes[0].dim;
+    c->m = ncomp(params->eq, c->dim);
+    c->params = *params;
+    c->meshes.assign(meshes, meshes + n_inst);
+    c->state = d_state;
+    c->ws = static_cast<char *>(d_workspace);
+    c->lay = make_layout(meshes, n_inst, params);
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    DevParams &dp = c->dp;
+    dp.gamma = params->gamma;
+    dp.adv_a = params->adv_a;
+    dp.adv_b = params->adv_b;
+    dp.cfl = params->cfl;
+    dp.eps = params->eps;
+    dp.g1 = params->lin_w[0];
+    dp.g2 = params->lin_w[1];
+    dp.g3 = params->lin_w[2];
+    dp.charwise = params->charwise;
+    dp.weights = params->weights;
+
+    long long o = 0, co = 0;
+    std::vector<Inst1D> i1;
+    for (int i = 0; i < n_inst; ++i) {
+        const shw_mesh &m = meshes[i];
+        c->off.push_back(o);
+        c->cell_off.push_back(co);
+        if (c->dim == 1) {
+            Inst1D d{};
+            d.off = o;
+            d.cell_off = co;
+            d.n = m.nx;
+            d.bc_lo = m.bc[0];
+            d.bc_hi = m.bc[1];
+            d.dx = (m.x1 - m.x0) / m.nx;
+            i1.push_back(d);
+        }
+        o += (long long)state_doubles(&m, params->eq);
+        co += (long long)m.nx * m.ny;
+    }
+    // largest instances first: a greedy schedule of the persistent loop
+    std::vector<int> order(n_inst);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        double wa = (double)meshes[a].nx * meshes[a].ny, wb = (double)meshes[b].nx * meshes[b].ny;
+        return wa * wa > wb * wb;
+    });
+    shw_status s = SHW_OK;
+    if (c->dim == 1) {
+        s = c->hip(hipMemcpyAsync(c->ws + c->lay.inst, i1.data(), i1.size() * sizeof(Inst1D),
+                                  hipMemcpyHostToDevice, c->stream), "copy instances");
+        c->grid1d = loop1d_max_blocks(params->eq);
+    }
+    if (s == SHW_OK)
+        s = c->hip(hipMemcpyAsync(c->ws + c->lay.order, order.data(), n_inst * sizeof(int),
+                                  hipMemcpyHostToDevice, c->stream), "copy order");
+    if (s == SHW_OK)
+        s = c->hip(hipMemsetAsync(c->ws + c->lay.ist, 0, n_inst * sizeof(InstState), c->stream),
+                   "clear instance state");
+    if (s == SHW_OK)
+        s = c->hip(hipMemsetAsync(c->ws + c->lay.flags, 1, (size_t)co, c->stream), "set flags");
+    if (s == SHW_OK) s = c->hip(hipStreamSynchronize(c->stream), "create");
+    if (s != SHW_OK) {
+        delete c;
+        return s;
+    }
+    *out = c;
+    return SHW_OK;
+}
+
+void shw_destroy(shw_ctx *ctx) { delete ctx; }
+
+shw_status shw_set_state(shw_ctx *c, int inst, const double *src, int on_device)
+{
+    if (!c || !src || inst < 0 || inst >= c->n_inst) return SHW_EINVAL;
+    size_t n = state_doubles(&c->meshes[inst], c->params.eq);
+    shw_status s = c->hip(hipMemcpyAsync(c->state + c->off[inst], src, n * sizeof(double),
+                                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                         c->stream), "set_state");
+    if (s != SHW_OK) return s;
+    // clear the sticky non-physical flag of this instance
+    s = c->hip(hipMemsetAsync(reinterpret_cast<char *>(c->ist() + inst) + offsetof(InstState, code),
+                              0, sizeof(int), c->stream), "set_state flag");
+    if (s != SHW_OK) return s;
+    if (!on_device) return c->hip(hipStreamSynchronize(c->stream), "set_state sync");
+    return SHW_OK;
+}
+
+shw_status shw_get_state(shw_ctx *c, int inst, double *dst, int on_device)
+{
+    if (!c || !dst || inst < 0 || inst >= c->n_inst) return SHW_EINVAL;
+    size_t n = state_doubles(&c->meshes[inst], c->params.eq);
+    shw_status s = c->hip(hipMemcpyAsync(dst, c->state + c->off[inst], n * sizeof(double),
+                                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                         c->stream), "get_state");
+    if (s != SHW_OK || on_device) return s;
+    return c->hip(hipStreamSynchronize(c->stream), "get_state sync");
+}
+
+static shw_status read_ist(shw_ctx *c, std::vector<InstState> &h)
+{
+    h.resize(c->n_inst);
+    shw_status s = c->hip(hipMemcpyAsync(h.data(), c->ist(), c->n_inst * sizeof(InstState),
+                                         hipMemcpyDeviceToHost, c->stream), "read times");
+    if (s != SHW_OK) return s;
+    return c->hip(hipStreamSynchronize(c->stream), "read times sync");
+}
+
+shw_status shw_get_time(shw_ctx *c, double *t, long long *steps)
+{
+    if (!c) return SHW_EINVAL;
+    std::vector<InstState> h;
+    shw_status s = read_ist(c, h);
+    if (s != SHW_OK) return s;
+    for (int i = 0; i < c->n_inst; ++i) {
+        if (t) t[i] = h[i].t;
+        if (steps) steps[i] = h[i].steps;
+    }
+    return SHW_OK;
+}
+
+shw_status shw_set_time(shw_ctx *c, const double *t)
+{
+    if (!c || !t) return SHW_EINVAL;
+    std::vector<InstState> h;
+    shw_status s = read_ist(c, h);
+    if (s != SHW_OK) return s;
+    for (int i = 0; i < c->n_inst; ++i) h[i].t = t[i];
+    s = c->hip(hipMemcpyAsync(c->ist(), h.data(), c->n_inst * sizeof(InstState),
+                              hipMemcpyHostToDevice, c->stream), "set_time");
+    if (s != SHW_OK) return s;
+    return c->hip(hipStreamSynchronize(c->stream), "set_time sync");
+}
+
+shw_status shw_compute_dt(shw_ctx *c, double *dt)
+{
+    if (!c || !dt) return SHW_EINVAL;
+    double *d_dt = c->at<double>(c->lay.dt);
+    shw_status s;
+    if (c->dim == 1) {
+        s = c->hip(launch_dt1d(c->params.eq, c->at<Inst1D>(c->lay.inst), c->n_inst, c->state,
+                               c->dp, d_dt, c->stream), "dt1d");
+    } else {
+        return c->fail(SHW_ESTATE, "2D not built yet");
+    }
+    if (s != SHW_OK) return s;
+    s = c->hip(hipMemcpyAsync(dt, d_dt, c->n_inst * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream), "dt copy");
+    if (s != SHW_OK) return s;
+    s = c->hip(hipStreamSynchronize(c->stream), "dt sync");
+    if (s != SHW_OK) return s;
+    for (int i = 0; i < c->n_inst; ++i)
+        if (!(dt[i] > 0.0)) {
+            c->bad_instance = i;
+            return c->fail(SHW_ENONPHYS, "non-physical cell average");
+        }
+    return SHW_OK;
+}
+
+static Loop1D loop_args(shw_ctx *c)
+{
+    Loop1D L{};
+    L.inst = c->at<Inst1D>(c->lay.inst);
+    L.n_inst = c->n_inst;
+    L.order = c->at<int>(c->lay.order);
+    L.queue = c->at<int>(c->lay.queue);
+    L.state = c->state;
+    L.alt = c->alt();
+    L.ist = c->ist();
+    L.flags = c->at<uint8_t>(c->lay.flags);
+    return L;
+}
+
+shw_status shw_step(shw_ctx *c, const double *dt)
+{
+    if (!c || !dt) return SHW_EINVAL;
+    for (int i = 0; i < c->n_inst; ++i)
+        if (!std::isfinite(dt[i])) return SHW_EINVAL;
+    double *d_dt = c->at<double>(c->lay.dt);
+    shw_status s = c->hip(hipMemcpyAsync(d_dt, dt, c->n_inst * sizeof(double),
+                                         hipMemcpyHostToDevice, c->stream), "step dt");
+    if (s != SHW_OK) return s;
+    if (c->dim != 1) return c->fail(SHW_ESTATE, "2D not built yet");
+    Loop1D L = loop_args(c);
+    L.dt_fixed = d_dt;
+    L.t_end = nullptr;
+    L.max_steps = 1;
+    int grid = std::min(c->grid1d, c->n_inst);
+    return c->hip(launch_loop1d(c->params.eq, L, c->dp, grid, c->stream), "step");
+}
+
+shw_status shw_advance_to(shw_ctx *c, const double *T, long long max_steps, long long *steps_out)
+{
+    if (!c || !T || max_steps < 0) return SHW_EINVAL;
+    for (int i = 0; i < c->n_inst; ++i)
+        if (!std::isfinite(T[i])) return SHW_EINVAL;
+    std::vector<InstState> before;
+    shw_status s = read_ist(c, before);
+    if (s != SHW_OK) return s;
+    double *d_T = c->at<double>(c->lay.t_end);
+    s = c->hip(hipMemcpyAsync(d_T, T, c->n_inst * sizeof(double), hipMemcpyHostToDevice,
+                              c->stream), "advance T");
+    if (s != SHW_OK) return s;
+    if (c->dim != 1) return c->fail(SHW_ESTATE, "2D not built yet");
+    Loop1D L = loop_args(c);
+    L.dt_fixed = nullptr;
+    L.t_end = d_T;
+    L.max_steps = max_steps;
+    int grid = std::min(c->grid1d, c->n_inst);
+    s = c->hip(launch_loop1d(c->params.eq, L, c->dp, grid, c->stream), "advance");
+    if (s != SHW_OK) return s;
+    std::vector<InstState> after;
+    s = read_ist(c, after);
+    if (s != SHW_OK) return s;
+    shw_status r = SHW_OK;
+    for (int i = 0; i < c->n_inst; ++i) {
+        if (steps_out) steps_out[i] = after[i].steps - before[i].steps;
+        if (after[i].code != 0 && r == SHW_OK) {
+            c->bad_instance = i;
+            r = c->fail(SHW_ENONPHYS, "non-physical cell average in instance " + std::to_string(i));
+        }
+    }
+    return r;
+}
+
+shw_status shw_set_flags(shw_ctx *c, int inst, const uint8_t *flags)
+{
+    if (!c || !flags || inst < 0 || inst >= c->n_inst) return SHW_EINVAL;
+    size_t n = (size_t)c->meshes[inst].nx * c->meshes[inst].ny;
+    shw_status s = c->hip(hipMemcpyAsync(c->ws + c->lay.flags + c->cell_off[inst], flags, n,
+                                         hipMemcpyHostToDevice, c->stream), "set_flags");
+    if (s != SHW_OK) return s;
+    return c->hip(hipStreamSynchronize(c->stream), "set_flags sync");
+}
+
+shw_status shw_status_detail(shw_ctx *c, int *bad_instance, char *msg, size_t msg_len)
+{
+    if (!c) return SHW_EINVAL;
+    if (bad_instance) *bad_instance = c->bad_instance;
+    if (msg && msg_len) {
+        std::strncpy(msg, c->msg.c_str(), msg_len - 1);
+        msg[msg_len - 1] = 0;
+    }
+    return SHW_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,192 @@
+"""GPU parity of the 1D path (batched persistent time loop) against the CPU
+oracle: element-by-element, relative L-infinity per quantity <= 1e-11
+(max |gpu - oracle| / max |oracle| over each of W and V)."""
+import concurrent.futures as cf
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2304_09724_amd as S
+from paper_2304_09724_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+def rel_err(g, o):
+    g, o = np.asarray(g), np.asarray(o)
+    errs = []
+    for q in range(o.shape[0]):
+        scale = max(np.abs(o[q]).max(), 1e-300)
+        errs.append(np.abs(g[q] - o[q]).max() / scale)
+    return max(errs)
+
+
+def ocfg(eq, bc=O.BC_PERIODIC, weights=O.W_NONLINEAR, charwise=True, adv_a=1.0):
+    return O.Config(eq=eq, bc=(bc,) * 4, weights=weights, charwise=charwise, adv_a=adv_a)
+
+
+def gparams(eq, weights=S.W_NONLINEAR, charwise=True, adv_a=1.0, cfl=0.9):
+    return S.Params.make(eq=eq, weights=weights, charwise=charwise, adv_a=adv_a, cfl=cfl)
+
+
+def run_gpu(meshes, params, states, T):
+    s = S.Solver(meshes, params)
+    for i, st in enumerate(states):
+        s.set_state(i, st)
+    steps = s.advance_to(T)
+    return s, [s.get_state(i) for i in range(len(states))], steps
+
+
+def test_linear_advection_full_run():
+    """u_t + u_x = 0, sin(pi x), N = 200, t = 2, CFL 0.3 (the small 1D case)."""
+    n = 200
+    st = WL.sine_advection(n)
+    s, (g,), steps = run_gpu([S.Mesh.line(n, 0.0, 2.0)], gparams(S.ADVECTION, cfl=0.3), [st], 2.0)
+    o, t, osteps, bad = O.advance1d(ocfg(O.ADVECTION), st, 2.0 / n, 0.3, 2.0)
+    assert steps[0] == osteps == 667
+    assert rel_err(g, o) < TOL
+    t_g, _ = s.times()
+    assert t_g[0] == 2.0
+    e = np.abs(g[0, 0] - WL.sine_advection_exact(n, 2.0))
+    assert e.mean() < 5e-10 and e.max() < 8e-10
+
+
+@pytest.mark.parametrize("n", [10, 40])
+def test_euler_density_wave_full_run(n):
+    st = WL.density_wave_1d(n)
+    _, (g,), steps = run_gpu([S.Mesh.line(n, 0.0, 2.0)], gparams(S.EULER), [st], 10.0)
+    o, t, osteps, bad = O.advance1d(ocfg(O.EULER), st, 2.0 / n, 0.9, 10.0)
+    assert steps[0] == osteps
+    assert rel_err(g, o) < TOL
+
+
+@pytest.mark.parametrize("n", [3, 4, 61, 62, 63, 64, 124, 125, 250])
+@pytest.mark.parametrize("bc", [S.BC_PERIODIC, S.BC_TRANSMISSIVE, S.BC_REFLECTIVE])
+def test_single_step_chunk_edges_and_boundaries(n, bc):
+    """One fixed step on random smooth data: sizes around the 62-cell chunk
+    and the smallest mesh, every boundary condition."""
+    rng = np.random.default_rng(n * 7 + bc)
+    x = (np.arange(n) + 0.5) / n
+    W = WL.prim_to_cons(1 + 0.2 * np.sin(2 * np.pi * x + rng.uniform(0, 6)),
+                        0.3 * np.cos(2 * np.pi * x), 1 + 0.1 * np.cos(4 * np.pi * x))
+    V = rng.normal(size=W.shape) * 0.3
+    st = np.stack([W, V])
+    dx = 1.0 / n
+    dt = 0.2 * dx
+    s = S.Solver([S.Mesh.line(n, 0.0, 1.0, bc)], gparams(S.EULER))
+    s.set_state(0, st)
+    s.step([dt])
+    g = s.get_state(0)
+    o, bad = O.step1d(ocfg(O.EULER, bc), st, dx, dt)
+    assert rel_err(g, o) < TOL
+
+
+@pytest.mark.parametrize("weights,charwise", [(S.W_LINEAR, True), (S.W_NONLINEAR, False),
+                                              (S.W_GATED, True)])
+def test_weight_modes(weights, charwise):
+    rng = np.random.default_rng(5)
+    n = 150
+    st = WL.riemann_1d(n, (1.0, 0.2, 1.0), (0.3, -0.1, 0.4))
+    flags = (rng.uniform(size=n) < 0.3).astype(np.uint8)
+    s = S.Solver([S.Mesh.line(n, 0.0, 1.0, S.BC_TRANSMISSIVE)], gparams(S.EULER, weights, charwise))
+    s.set_state(0, st)
+    if weights == S.W_GATED:
+        s.set_flags(0, flags)
+    dt = 0.3 / n
+    for _ in range(5):
+        s.step([dt])
+    g = s.get_state(0)
+    cfg = ocfg(O.EULER, O.BC_TRANSMISSIVE, weights, charwise)
+    o = st
+    for _ in range(5):
+        o, bad = O.step1d(cfg, o, 1.0 / n, dt, flags if weights == S.W_GATED else None)
+    assert rel_err(g, o) < TOL
+
+
+def test_burgers_full_run():
+    n = 80
+    st = WL.burgers_sine(n)
+    T = 0.5 / np.pi
+    _, (g,), steps = run_gpu([S.Mesh.line(n, 0.0, 2.0)], gparams(S.BURGERS), [st], T)
+    o, t, osteps, bad = O.advance1d(ocfg(O.BURGERS), st, 2.0 / n, 0.9, T)
+    assert steps[0] == osteps
+    assert rel_err(g, o) < TOL
+
+
+def test_compute_dt_matches_oracle():
+    insts = WL.riemann_batch_1d(count=6, nmin=40, nmax=200)
+    s = S.Solver([S.Mesh.line(d.n, d.x0, d.x1, S.BC_TRANSMISSIVE) for d in insts], gparams(S.EULER))
+    for i, d in enumerate(insts):
+        s.set_state(i, d.state())
+    dt = s.compute_dt()
+    for i, d in enumerate(insts):
+        want = O.dt1d(ocfg(O.EULER, O.BC_TRANSMISSIVE), d.state(), d.dx, 0.9)
+        assert dt[i] == pytest.approx(want, rel=1e-14)
+
+
+def test_ragged_riemann_batch_full_runs():
+    """A ragged batch of Riemann problems (the batched workload's recipe with
+    smaller meshes), each advanced to t = 0.14 with its own CFL steps."""
+    insts = WL.riemann_batch_1d(count=12, seed=7, nmin=20, nmax=300)
+    meshes = [S.Mesh.line(d.n, d.x0, d.x1, S.BC_TRANSMISSIVE) for d in insts]
+    s, g, steps = run_gpu(meshes, gparams(S.EULER), [d.state() for d in insts], 0.14)
+    cfg = ocfg(O.EULER, O.BC_TRANSMISSIVE)
+
+    def one(i):
+        d = insts[i]
+        return O.advance1d(cfg, d.state(), d.dx, 0.9, 0.14)
+
+    with cf.ThreadPoolExecutor(8) as ex:
+        res = list(ex.map(one, range(len(insts))))
+    for i, (o, t, osteps, bad) in enumerate(res):
+        assert steps[i] == osteps, i
+        assert rel_err(g[i], o) < TOL, i
+
+
+def test_nonphysical_state_is_reported_and_isolated():
+    n = 50
+    good = WL.density_wave_1d(n)
+    badst = good.copy()
+    badst[0, 0, 17] = -1.0          # negative density
+    s = S.Solver([S.Mesh.line(n, 0.0, 2.0)] * 2, gparams(S.EULER))
+    s.set_state(0, badst)
+    s.set_state(1, good)
+    with pytest.raises(S.ShwError) as e:
+        s.advance_to(0.1)
+    assert e.value.code == -4 and e.value.bad_instance == 0
+    o, *_ = O.advance1d(ocfg(O.EULER), good, 2.0 / n, 0.9, 0.1)
+    assert rel_err(s.get_state(1), o) < TOL
+
+
+def test_invalid_arguments_are_rejected():
+    with pytest.raises(S.ShwError):
+        S.Solver([S.Mesh.line(2, 0.0, 1.0)], gparams(S.EULER))       # too few cells
+    with pytest.raises(S.ShwError):
+        S.Solver([S.Mesh.line(10, 1.0, 0.0)], gparams(S.EULER))      # empty interval
+    p = gparams(S.EULER)
+    p.lin_w[0] = 0.5                                                   # weights must sum to 1
+    with pytest.raises(S.ShwError):
+        S.Solver([S.Mesh.line(10, 0.0, 1.0)], p)
+
+
+def test_restart_from_checkpoint_is_bitwise():
+    """(state, t) is a complete checkpoint: N + N steps with a restore in
+    between equals 2N steps exactly."""
+    n = 100
+    st = WL.riemann_1d(n, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+    m = [S.Mesh.line(n, 0.0, 1.0, S.BC_TRANSMISSIVE)]
+    a = S.Solver(m, gparams(S.EULER))
+    a.set_state(0, st)
+    a.advance_to(1.0, max_steps=40)
+    ref = a.get_state(0)
+    b = S.Solver(m, gparams(S.EULER))
+    b.set_state(0, st)
+    b.advance_to(1.0, max_steps=20)
+    ck, (t, _) = b.get_state(0), b.times()
+    c = S.Solver(m, gparams(S.EULER))
+    c.set_state(0, ck)
+    c.set_times(t)
+    c.advance_to(1.0, max_steps=20)
+    assert np.array_equal(c.get_state(0), ref)
