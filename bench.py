@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Throughput of the batched 1D Euler ADER-SHWENO time loop on one MI355X.
+
+Workload: 4096 independent 1D Euler Riemann problems on [0,1] (gamma 1.4),
+N even and uniform in {200..2000} cells per instance, left/right rho, p ~
+U[0.1, 2], u ~ U[-1, 1] (seeded), jump at x = 0.5, transmissive ends,
+advanced to t = 0.14 with CFL 0.9 in one persistent launch.  One bench step =
+the whole job: reset the batch to its initial state and advance every
+instance to t = 0.14.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line (metric, value = cell-updates/s, roofline of the
+persistent kernel, CPU-oracle baseline on a bounded sample).
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+T_END = 0.14
+COUNT = 4096
+# FP64 flops of one 1D Euler cell-update of the sweep (reconstruction of one
+# cell in characteristic fields with nonlinear weights, GRP at one face,
+# 4-point Lobatto flux, update), FMA counted as 2; counted from the kernel's
+# own templated arithmetic by paper_2304_09724_amd/flopcount.
+FLOPS_PER_CELL_UPDATE = None
+FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X, dense FP64 vector
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def flops_per_cell_update():
+    global FLOPS_PER_CELL_UPDATE
+    if FLOPS_PER_CELL_UPDATE is None:
+        from paper_2304_09724_amd import flopcount
+        FLOPS_PER_CELL_UPDATE = flopcount.euler1d_cell_update()["flops"]
+    return FLOPS_PER_CELL_UPDATE
+
+
+def make_batch():
+    from paper_2304_09724_amd import workloads as WL
+    insts = WL.riemann_batch_1d(count=COUNT, T=T_END)
+    states = [d.state() for d in insts]
+    return insts, states
+
+
+def cpu_baseline(insts, states, budget_threads=None):
+    """The CPU oracle, as it stands, on a bounded sample of the same batch:
+    the first 16 instances (seeded order) with N <= 800, each run in full to
+    t = 0.14 on its own host thread."""
+    import oracle as O
+    sample = [i for i, d in enumerate(insts) if d.n <= 800][:16]
+    threads = min(len(sample), budget_threads or os.cpu_count() or 1)
+    cfg = O.Config(eq=O.EULER, bc=(O.BC_TRANSMISSIVE,) * 4)
+
+    def one(i):
+        o, t, steps, bad = O.advance1d(cfg, states[i], insts[i].dx, 0.9, T_END)
+        return insts[i].n * steps
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        cu = sum(ex.map(one, sample))
+    wall = time.perf_counter() - t0
+    return {"value": cu / wall, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(sample)} instances of the seeded batch with N <= 800 "
+                      f"({cu} cell-updates, full runs to t={T_END}), one host thread each, "
+                      f"{wall:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the batch would be "
+                                   "sharded by instance across GPUs with no communication "
+                                   "(see the multi-GPU design notes)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_2304_09724_amd as S
+
+    log("building the batch ...")
+    insts, states = make_batch()
+    meshes = [S.Mesh.line(d.n, d.x0, d.x1, S.BC_TRANSMISSIVE) for d in insts]
+    solver = S.Solver(meshes, S.Params.make(eq=S.EULER, cfl=0.9), device="cuda:0")
+    init = torch.from_numpy(np.concatenate([s.reshape(-1) for s in states])).to("cuda:0")
+    stream = solver.stream
+    zeros = np.zeros(COUNT)
+    T = np.full(COUNT, T_END)
+    ncell = np.array([d.n for d in insts], dtype=np.int64)
+
+    def one_step():
+        solver.state.copy_(init)
+        solver.set_times(zeros)
+        return solver.advance_to(T, raise_nonphysical=False)
+
+    log(f"warmup x{args.warmup} ...")
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    cell_updates = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        solver.state.copy_(init)
+        solver.set_times(zeros)
+        ev[k][0].record(stream)
+        steps = solver.advance_to(T, raise_nonphysical=False)
+        ev[k][1].record(stream)
+        cell_updates.append(int((ncell * steps).sum()))
+        log(f"step {k}: {cell_updates[-1]} cell-updates")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    codes = solver.instance_status()
+    nonphys = int((codes != 0).sum())
+    cu_step = float(np.mean(cell_updates))
+    value = cu_step * args.steps / wall
+
+    flops = flops_per_cell_update()
+    achieved_tflops = flops * cu_step / (kernel_ms * 1e-3) / 1e12
+    algo_bytes = 2 * 2 * 3 * 8           # read + write of W and V (3 components) per cell-update
+    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3),
+                "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved_tflops / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": "loop1d_kernel<EULER> (persistent batched time loop)",
+                "kernel_ms": round(kernel_ms, 3), "flops_per_cell_update": flops,
+                "hbm_algorithmic_GBs": round(algo_bytes * cu_step / (kernel_ms * 1e-3) / 1e9, 1),
+                "hbm_frac": round(algo_bytes * cu_step / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    out = {"metric": "cell-updates/sec FP64 (plain vs learned-gated, batched) at fixed L1 error",
+           "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded Riemann problems)",
+           "config": {"workload": "1D Euler batch: 4096 Riemann problems, N in {200..2000}, "
+                                  "t=0.14, CFL 0.9, transmissive, plain nonlinear weights",
+                      "instances": COUNT, "cell_updates_per_step": cu_step,
+                      "nonphysical_instances": nonphys,
+                      "nonphysical_note": "instances on which the unlimited scheme (no "
+                                          "positivity limiter, as in the paper) meets a "
+                                          "non-physical state stop there; only the cell-"
+                                          "updates actually performed are counted",
+                      "parallelism": "single GPU, one persistent launch"},
+           "roofline": roofline}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(insts, states)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -143,6 +143,10 @@ shw_status shw_advance_to(shw_ctx *ctx, const double *T, long long max_steps,
  * gate is evaluated again. */
 shw_status shw_set_flags(shw_ctx *ctx, int inst, const uint8_t *flags);
 
+/* Per-instance status (host array of n_inst): SHW_OK, or SHW_ENONPHYS for an
+ * instance that met a non-physical state and stopped.  Synchronising. */
+shw_status shw_instance_status(shw_ctx *ctx, int *codes);
+
 /* First failing instance and a message for the last error (any may be
  * NULL). */
 shw_status shw_status_detail(shw_ctx *ctx, int *bad_instance, char *msg, size_t msg_len);

@@ -87,6 +87,7 @@ def lib():
         L.shw_compute_dt.argtypes = [vp, _D]
         L.shw_step.argtypes = [vp, _D]
         L.shw_advance_to.argtypes = [vp, _D, ctypes.c_longlong, _LL]
+        L.shw_instance_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
         L.shw_set_flags.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8)]
         L.shw_status_detail.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_char_p,
                                         ctypes.c_size_t]
@@ -170,6 +171,12 @@ class Solver:
         self._check(lib().shw_get_time(self.ctx, _dptr(t), s.ctypes.data_as(_LL)))
         return t, s
 
+    def instance_status(self):
+        """Per instance: 0 ok, -4 (SHW_ENONPHYS) stopped on a non-physical state."""
+        codes = np.zeros(self.n, dtype=np.int32)
+        self._check(lib().shw_instance_status(self.ctx, codes.ctypes.data_as(ctypes.POINTER(ctypes.c_int))))
+        return codes
+
     def set_times(self, t):
         t = np.ascontiguousarray(np.broadcast_to(np.asarray(t, float), (self.n,)))
         self._check(lib().shw_set_time(self.ctx, _dptr(t)))
@@ -183,10 +190,15 @@ class Solver:
         dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, float), (self.n,)))
         self._check(lib().shw_step(self.ctx, _dptr(dt)))
 
-    def advance_to(self, T, max_steps=1_000_000):
+    def advance_to(self, T, max_steps=1_000_000, raise_nonphysical=True):
+        """Advance instance i to T[i]; returns the steps taken per instance.
+        With raise_nonphysical=False a non-physical instance does not raise
+        (see instance_status())."""
         T = np.ascontiguousarray(np.broadcast_to(np.asarray(T, float), (self.n,)))
         steps = np.zeros(self.n, dtype=np.int64)
-        self._check(lib().shw_advance_to(self.ctx, _dptr(T), max_steps, steps.ctypes.data_as(_LL)))
+        code = lib().shw_advance_to(self.ctx, _dptr(T), max_steps, steps.ctypes.data_as(_LL))
+        if not (code == -4 and not raise_nonphysical):
+            self._check(code)
         return steps
 
     def set_flags(self, i, flags):

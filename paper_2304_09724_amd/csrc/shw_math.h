@@ -8,6 +8,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Every arithmetic routine is a template on the real type R: the kernels use
+// R = double; a host build with an operation-counting type measures the
+// algorithmic flop count of exactly this code.
+#define SHW_HD __host__ __device__ __forceinline__
+
 namespace shw {
 
 enum { ADV = 0, BURG = 1, EULER = 2 };
@@ -44,10 +49,10 @@ constexpr double LOB_W1 = 5.0 / 12.0;
 // Quartic whose averages over cells -1, 0, 1 and whose increments
 // p(l+1/2) - p(l-1/2) over cells -1, +1 match the data (solved by hand from
 // those five linear conditions).
-__device__ __forceinline__ void big_quartic(double am, double a0, double ap,
-                                            double bm, double bp, double c[5])
+template <class R>
+SHW_HD void big_quartic(R am, R a0, R ap, R bm, R bp, R c[5])
 {
-    const double s = am + ap, d = ap - am, bs = bm + bp, bd = bp - bm;
+    const R s = am + ap, d = ap - am, bs = bm + bp, bd = bp - bm;
     c[0] = (1148.0 * a0 - 94.0 * s + 27.0 * bd) * (1.0 / 960.0);
     c[1] = (13.0 * d - 5.0 * bs) * (1.0 / 16.0);
     c[2] = (10.0 * s - 20.0 * a0 - 3.0 * bd) * (1.0 / 8.0);
@@ -61,21 +66,20 @@ __device__ __forceinline__ void big_quartic(double am, double a0, double ap,
 // the quadratic form below (exact integration of the squared derivatives).
 // Simple-WENO weights: tau = ((|b1-b2| + |b1-b3|)/2)^2,
 // w_l ~ g_l (1 + tau/(b_l + eps)).
-__device__ __forceinline__ void nonlinear_weights(const double c[5], double am, double a0,
-                                                  double ap, const DevParams &P,
-                                                  double w[3])
+template <class R>
+SHW_HD void nonlinear_weights(const R c[5], R am, R a0, R ap, const DevParams &P, R w[3])
 {
-    const double b1 = c[1] * c[1] + 0.5 * c[1] * c[3] + (13.0 / 3.0) * c[2] * c[2]
+    const R b1 = c[1] * c[1] + 0.5 * c[1] * c[3] + (13.0 / 3.0) * c[2] * c[2]
                     + (21.0 / 5.0) * c[2] * c[4] + (3129.0 / 80.0) * c[3] * c[3]
                     + (87617.0 / 140.0) * c[4] * c[4];
-    const double dl = a0 - am, dr = ap - a0;
-    const double b2 = dl * dl, b3 = dr * dr;
-    double tau = 0.5 * (fabs(b1 - b2) + fabs(b1 - b3));
+    const R dl = a0 - am, dr = ap - a0;
+    const R b2 = dl * dl, b3 = dr * dr;
+    R tau = 0.5 * (fabs(b1 - b2) + fabs(b1 - b3));
     tau = tau * tau;
-    const double w1 = P.g1 * (1.0 + tau / (b1 + P.eps));
-    const double w2 = P.g2 * (1.0 + tau / (b2 + P.eps));
-    const double w3 = P.g3 * (1.0 + tau / (b3 + P.eps));
-    const double inv = 1.0 / (w1 + w2 + w3);
+    const R w1 = P.g1 * (1.0 + tau / (b1 + P.eps));
+    const R w2 = P.g2 * (1.0 + tau / (b2 + P.eps));
+    const R w3 = P.g3 * (1.0 + tau / (b3 + P.eps));
+    const R inv = 1.0 / (w1 + w2 + w3);
     w[0] = w1 * inv;
     w[1] = w2 * inv;
     w[2] = w3 * inv;
@@ -83,11 +87,11 @@ __device__ __forceinline__ void nonlinear_weights(const double c[5], double am, 
 
 // Final polynomial (w1/g1)(p1 - g2 p2 - g3 p3) + w2 p2 + w3 p3 in place of the
 // quartic coefficients c (the linear candidates only touch xi^0 and xi^1).
-__device__ __forceinline__ void combine(double c[5], double am, double a0, double ap,
-                                        const double w[3], const DevParams &P)
+template <class R>
+SHW_HD void combine(R c[5], R am, R a0, R ap, const R w[3], const DevParams &P)
 {
-    const double f = w[0] / P.g1;
-    const double dl = a0 - am, dr = ap - a0;
+    const R f = w[0] / P.g1;
+    const R dl = a0 - am, dr = ap - a0;
     c[0] = f * (c[0] - (P.g2 + P.g3) * a0) + (w[1] + w[2]) * a0;
     c[1] = f * (c[1] - P.g2 * dl - P.g3 * dr) + w[1] * dl + w[2] * dr;
     c[2] *= f;
@@ -96,12 +100,13 @@ __device__ __forceinline__ void combine(double c[5], double am, double a0, doubl
 }
 
 // d^k p/dxi^k at xi = -1/2 (lo) and xi = +1/2 (hi), k = 0..4.
-__device__ __forceinline__ void edge_derivs(const double c[5], double lo[5], double hi[5])
+template <class R>
+SHW_HD void edge_derivs(const R c[5], R lo[5], R hi[5])
 {
-    const double e0 = c[0] + 0.25 * c[2] + 0.0625 * c[4], o0 = 0.5 * c[1] + 0.125 * c[3];
-    const double e1 = c[1] + 0.75 * c[3], o1 = c[2] + 0.5 * c[4];
-    const double e2 = 2.0 * c[2] + 3.0 * c[4], o2 = 3.0 * c[3];
-    const double e3 = 6.0 * c[3], o3 = 12.0 * c[4];
+    const R e0 = c[0] + 0.25 * c[2] + 0.0625 * c[4], o0 = 0.5 * c[1] + 0.125 * c[3];
+    const R e1 = c[1] + 0.75 * c[3], o1 = c[2] + 0.5 * c[4];
+    const R e2 = 2.0 * c[2] + 3.0 * c[4], o2 = 3.0 * c[3];
+    const R e3 = 6.0 * c[3], o3 = 12.0 * c[4];
     hi[0] = e0 + o0; lo[0] = e0 - o0;
     hi[1] = e1 + o1; lo[1] = e1 - o1;
     hi[2] = e2 + o2; lo[2] = e2 - o2;
@@ -113,8 +118,8 @@ __device__ __forceinline__ void edge_derivs(const double c[5], double lo[5], dou
 // Euler equations (sec. 5, eqs. (Euler) and (2d)): E = p/(g-1) + rho|u|^2/2.
 // ---------------------------------------------------------------------------
 
-template <int DIM>
-__device__ __forceinline__ double pressure(const double *W, double gamma)
+template <int DIM, class R>
+SHW_HD R pressure(const R *W, double gamma)
 {
     if constexpr (DIM == 1) {
         return (gamma - 1.0) * (W[2] - 0.5 * W[1] * W[1] / W[0]);
@@ -126,20 +131,18 @@ __device__ __forceinline__ double pressure(const double *W, double gamma)
 // Eigenvectors of the flux Jacobian in direction DIR (0 = x, 1 = y) at W.
 // R has the right eigenvectors as columns (speeds un-c, un, [un,] un+c), L =
 // R^{-1} in closed form, with b1 = (g-1)/c^2 and b2 = b1 |u|^2 / 2.
-template <int DIM, int DIR>
-__device__ __forceinline__ void euler_eigen(const double *W, double gamma,
-                                            double R[][NComp<EULER, DIM>::M],
-                                            double L[][NComp<EULER, DIM>::M],
-                                            double lam[NComp<EULER, DIM>::M])
+template <int DIM, int DIR, class Re>
+SHW_HD void euler_eigen(const Re *W, double gamma, Re R[][NComp<EULER, DIM>::M],
+                        Re L[][NComp<EULER, DIM>::M], Re lam[NComp<EULER, DIM>::M])
 {
-    const double ir = 1.0 / W[0];
-    const double u = W[1] * ir;
+    const Re ir = 1.0 / W[0];
+    const Re u = W[1] * ir;
     if constexpr (DIM == 1) {
-        const double p = (gamma - 1.0) * (W[2] - 0.5 * W[1] * u);
-        const double c2 = gamma * p * ir;
-        const double c = sqrt(c2), ic = 1.0 / c;
-        const double H = (W[2] + p) * ir;
-        const double b1 = (gamma - 1.0) / c2, b2 = 0.5 * b1 * u * u;
+        const Re p = (gamma - 1.0) * (W[2] - 0.5 * W[1] * u);
+        const Re c2 = gamma * p * ir;
+        const Re c = sqrt(c2), ic = 1.0 / c;
+        const Re H = (W[2] + p) * ir;
+        const Re b1 = (gamma - 1.0) / c2, b2 = 0.5 * b1 * u * u;
         R[0][0] = 1.0;       R[0][1] = 1.0;         R[0][2] = 1.0;
         R[1][0] = u - c;     R[1][1] = u;           R[1][2] = u + c;
         R[2][0] = H - u * c; R[2][1] = 0.5 * u * u; R[2][2] = H + u * c;
@@ -148,15 +151,15 @@ __device__ __forceinline__ void euler_eigen(const double *W, double gamma,
         L[2][0] = 0.5 * (b2 - u * ic); L[2][1] = -0.5 * (b1 * u - ic); L[2][2] = 0.5 * b1;
         lam[0] = u - c; lam[1] = u; lam[2] = u + c;
     } else {
-        const double v = W[2] * ir;
-        const double q2 = u * u + v * v;
-        const double p = (gamma - 1.0) * (W[3] - 0.5 * W[0] * q2);
-        const double c2 = gamma * p * ir;
-        const double c = sqrt(c2), ic = 1.0 / c;
-        const double H = (W[3] + p) * ir;
-        const double b1 = (gamma - 1.0) / c2, b2 = 0.5 * b1 * q2;
+        const Re v = W[2] * ir;
+        const Re q2 = u * u + v * v;
+        const Re p = (gamma - 1.0) * (W[3] - 0.5 * W[0] * q2);
+        const Re c2 = gamma * p * ir;
+        const Re c = sqrt(c2), ic = 1.0 / c;
+        const Re H = (W[3] + p) * ir;
+        const Re b1 = (gamma - 1.0) / c2, b2 = 0.5 * b1 * q2;
         // normal (n) and tangential (s) velocity and momentum slots
-        const double un = DIR == 0 ? u : v, us = DIR == 0 ? v : u;
+        const Re un = DIR == 0 ? u : v, us = DIR == 0 ? v : u;
         constexpr int N = DIR == 0 ? 1 : 2, T = DIR == 0 ? 2 : 1;
         R[0][0] = 1.0; R[0][1] = 1.0; R[0][2] = 0.0; R[0][3] = 1.0;
         R[N][0] = un - c; R[N][1] = un; R[N][2] = 0.0; R[N][3] = un + c;
@@ -173,23 +176,23 @@ __device__ __forceinline__ void euler_eigen(const double *W, double gamma,
 }
 
 // Physical flux in x of a point state (scalar equations: a W or W^2/2).
-template <int EQ, int DIM>
-__device__ __forceinline__ void phys_flux_x(const double *W, const DevParams &P, double *F)
+template <int EQ, int DIM, class R>
+SHW_HD void phys_flux_x(const R *W, const DevParams &P, R *F)
 {
     if constexpr (EQ == ADV) {
         F[0] = P.adv_a * W[0];
     } else if constexpr (EQ == BURG) {
         F[0] = 0.5 * W[0] * W[0];
     } else if constexpr (DIM == 1) {
-        const double u = W[1] / W[0];
-        const double p = (P.gamma - 1.0) * (W[2] - 0.5 * W[1] * u);
+        const R u = W[1] / W[0];
+        const R p = (P.gamma - 1.0) * (W[2] - 0.5 * W[1] * u);
         F[0] = W[1];
         F[1] = W[1] * u + p;
         F[2] = (W[2] + p) * u;
     } else {
-        const double ir = 1.0 / W[0];
-        const double u = W[1] * ir;
-        const double p = (P.gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) * ir);
+        const R ir = 1.0 / W[0];
+        const R u = W[1] * ir;
+        const R p = (P.gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) * ir);
         F[0] = W[1];
         F[1] = W[1] * u + p;
         F[2] = W[2] * u;
@@ -200,20 +203,19 @@ __device__ __forceinline__ void phys_flux_x(const double *W, const DevParams &P,
 // HLLC Godunov state at x/t = 0 (leading term, sec. 2.1.1), Davis wave-speed
 // estimates, contact speed from the HLLC jump conditions; a state on a
 // boundary between two branches goes to the left one.
-template <int DIM>
-__device__ __forceinline__ void hllc_state(const double *WL, const double *WR,
-                                           double gamma, double *Ws)
+template <int DIM, class R>
+SHW_HD void hllc_state(const R *WL, const R *WR, double gamma, R *Ws)
 {
     constexpr int M = NComp<EULER, DIM>::M;
-    const double rl = WL[0], rr = WR[0];
-    const double irl = 1.0 / rl, irr = 1.0 / rr;
-    const double ul = WL[1] * irl, ur = WR[1] * irr;
-    const double pl = pressure<DIM>(WL, gamma), pr = pressure<DIM>(WR, gamma);
-    const double cl = sqrt(gamma * pl * irl), cr = sqrt(gamma * pr * irr);
-    const double SL = fmin(ul - cl, ur - cr);
-    const double SR = fmax(ul + cl, ur + cr);
-    const double ml = rl * (SL - ul), mr = rr * (SR - ur);
-    const double Ss = (pr - pl + ul * ml - ur * mr) / (ml - mr);
+    const R rl = WL[0], rr = WR[0];
+    const R irl = 1.0 / rl, irr = 1.0 / rr;
+    const R ul = WL[1] * irl, ur = WR[1] * irr;
+    const R pl = pressure<DIM>(WL, gamma), pr = pressure<DIM>(WR, gamma);
+    const R cl = sqrt(gamma * pl * irl), cr = sqrt(gamma * pr * irr);
+    const R SL = fmin(ul - cl, ur - cr);
+    const R SR = fmax(ul + cl, ur + cr);
+    const R ml = rl * (SL - ul), mr = rr * (SR - ur);
+    const R Ss = (pr - pl + ul * ml - ur * mr) / (ml - mr);
     if (0.0 <= SL) {
 #pragma unroll
         for (int c = 0; c < M; ++c) Ws[c] = WL[c];
@@ -225,10 +227,10 @@ __device__ __forceinline__ void hllc_state(const double *WL, const double *WR,
         return;
     }
     const bool left = 0.0 <= Ss;
-    const double *WK = left ? WL : WR;
-    const double rk = left ? rl : rr, uk = left ? ul : ur, pk = left ? pl : pr;
-    const double SK = left ? SL : SR, mk = left ? ml : mr;
-    const double f = mk / (SK - Ss);
+    const R *WK = left ? WL : WR;
+    const R rk = left ? rl : rr, uk = left ? ul : ur, pk = left ? pl : pr;
+    const R SK = left ? SL : SR, mk = left ? ml : mr;
+    const R f = mk / (SK - Ss);
     Ws[0] = f;
     Ws[1] = f * Ss;
     if constexpr (DIM == 2) Ws[2] = f * (WK[2] / rk);
@@ -238,20 +240,22 @@ __device__ __forceinline__ void hllc_state(const double *WL, const double *WR,
 // Upwind solution at x/t = 0 of a linear Riemann problem with speed lam; a
 // speed below 1e-10 of the system's fastest speed counts as zero and takes
 // the mean (a rounding-level speed must not pick a side).
-__device__ __forceinline__ double upwind(double lam, double scale, double l, double r)
+template <class R>
+SHW_HD R upwind(R lam, R scale, R l, R r)
 {
-    const double z = 1e-10 * scale;
+    const R z = 1e-10 * scale;
     return lam > z ? l : (lam < -z ? r : 0.5 * (l + r));
 }
 
 // Exact Godunov state of Burgers' equation at x/t = 0 (sec. 2.1.1, scalar case).
-__device__ __forceinline__ double burgers_state(double ul, double ur)
+template <class R>
+SHW_HD R burgers_state(R ul, R ur)
 {
     if (ul > ur) {
-        const double s = 0.5 * (ul + ur);
+        const R s = 0.5 * (ul + ur);
         return s > 0.0 ? ul : (s < 0.0 ? ur : s);
     }
-    return ul >= 0.0 ? ul : (ur <= 0.0 ? ur : 0.0);
+    return ul >= 0.0 ? ul : (ur <= 0.0 ? ur : R(0.0));
 }
 
 } // namespace shw

@@ -264,6 +264,16 @@ shw_status shw_get_time(shw_ctx *c, double *t, long long *steps)
     return SHW_OK;
 }
 
+shw_status shw_instance_status(shw_ctx *c, int *codes)
+{
+    if (!c || !codes) return SHW_EINVAL;
+    std::vector<InstState> h;
+    shw_status s = read_ist(c, h);
+    if (s != SHW_OK) return s;
+    for (int i = 0; i < c->n_inst; ++i) codes[i] = h[i].code ? SHW_ENONPHYS : SHW_OK;
+    return SHW_OK;
+}
+
 shw_status shw_set_time(shw_ctx *c, const double *t)
 {
     if (!c || !t) return SHW_EINVAL;

@@ -17,6 +17,7 @@
 // update their cells (Step 5, eq. (cons) and eqs. (derave), (tay1d)).  A
 // chunk advances 62 cells; lanes 0 and 63 only feed their neighbours.
 #include "shw_kernels.h"
+#include "sweep1d_math.h"
 
 namespace shw {
 
@@ -59,239 +60,6 @@ __device__ __forceinline__ int load_cell(const double *__restrict__ base, int n,
     return s;
 }
 
-// Step 1: reconstruction of one cell; lo/hi receive d^a W/dx^a at the left
-// and right edge, a = 0..4.
-template <int EQ, int M>
-__device__ __forceinline__ void recon_cell(const double Wm[M], const double W0[M],
-                                           const double Wp[M], const double Vm[M],
-                                           const double Vp[M], double dx, bool full,
-                                           const DevParams &P, double lo[5][M],
-                                           double hi[5][M])
-{
-    const double idx = 1.0 / dx;
-    double sc[5];
-    sc[0] = 1.0; sc[1] = idx; sc[2] = idx * idx; sc[3] = sc[2] * idx; sc[4] = sc[2] * sc[2];
-    if constexpr (EQ == EULER) {
-        if (full && P.charwise) {
-            double R[M][M], L[M][M], lam[M];
-            euler_eigen<1, 0>(W0, P.gamma, R, L, lam);
-            double clo[M][5], chi[M][5];
-#pragma unroll
-            for (int s = 0; s < M; ++s) {
-                double am = 0, a0 = 0, ap = 0, bm = 0, bp = 0;
-#pragma unroll
-                for (int c = 0; c < M; ++c) {
-                    am += L[s][c] * Wm[c];
-                    a0 += L[s][c] * W0[c];
-                    ap += L[s][c] * Wp[c];
-                    bm += L[s][c] * Vm[c];
-                    bp += L[s][c] * Vp[c];
-                }
-                double q[5], w[3];
-                big_quartic(am, a0, ap, dx * bm, dx * bp, q);
-                nonlinear_weights(q, am, a0, ap, P, w);
-                combine(q, am, a0, ap, w, P);
-                edge_derivs(q, clo[s], chi[s]);
-            }
-#pragma unroll
-            for (int a = 0; a < 5; ++a)
-#pragma unroll
-                for (int c = 0; c < M; ++c) {
-                    double l = 0.0, h = 0.0;
-#pragma unroll
-                    for (int s = 0; s < M; ++s) {
-                        l += R[c][s] * clo[s][a];
-                        h += R[c][s] * chi[s][a];
-                    }
-                    lo[a][c] = l * sc[a];
-                    hi[a][c] = h * sc[a];
-                }
-            return;
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-        double q[5], l5[5], h5[5];
-        big_quartic(Wm[c], W0[c], Wp[c], dx * Vm[c], dx * Vp[c], q);
-        if (full) {
-            double w[3];
-            nonlinear_weights(q, Wm[c], W0[c], Wp[c], P, w);
-            combine(q, Wm[c], W0[c], Wp[c], w, P);
-        }
-        edge_derivs(q, l5, h5);
-#pragma unroll
-        for (int a = 0; a < 5; ++a) {
-            lo[a][c] = l5[a] * sc[a];
-            hi[a][c] = h5[a] * sc[a];
-        }
-    }
-}
-
-// Lax-Wendroff procedure (sec. 2.1.2, eq. (ck)) as power series in (x, t):
-// w[c][a][k] is the coefficient of x^a t^k; the PDE W_t = -F(W)_x gives
-// (k+1) w[a][k+1] = -(a+1) F[a+1][k].  Time level by time level, every series
-// coefficient of the fluxes is formed once (products by the Cauchy rule).
-template <int EQ, int M>
-__device__ __forceinline__ void ck1d(double w[M][5][5], const DevParams &P)
-{
-    if constexpr (EQ == ADV) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int a = 0; a + k < 4; ++a)
-                w[0][a][k + 1] = -P.adv_a * (double)(a + 1) / (double)(k + 1) * w[0][a + 1][k];
-    } else if constexpr (EQ == BURG) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-            for (int a = 0; a + k < 4; ++a) {
-                // F = W^2/2 at (a+1, k)
-                double s = 0.0;
-#pragma unroll
-                for (int b = 0; b <= a + 1; ++b)
-#pragma unroll
-                    for (int j = 0; j <= k; ++j) s += w[0][b][j] * w[0][a + 1 - b][k - j];
-                w[0][a][k + 1] = -0.5 * (double)(a + 1) / (double)(k + 1) * s;
-            }
-    } else {
-        const double gm1 = P.gamma - 1.0;
-        double r[5][5], u[5][5], mu[5][5], p[5][5], ep[5][5], epu[5][5];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-#pragma unroll
-            for (int a = 0; a + k <= 4; ++a) {
-                if (a == 0 && k == 0) {
-                    r[0][0] = 1.0 / w[0][0][0];
-                } else {
-                    double s = 0.0;
-#pragma unroll
-                    for (int b = 0; b <= a; ++b)
-#pragma unroll
-                        for (int j = 0; j <= k; ++j)
-                            if (b + j > 0) s += w[0][b][j] * r[a - b][k - j];
-                    r[a][k] = -s * r[0][0];
-                }
-                double su = 0.0;
-#pragma unroll
-                for (int b = 0; b <= a; ++b)
-#pragma unroll
-                    for (int j = 0; j <= k; ++j) su += w[1][b][j] * r[a - b][k - j];
-                u[a][k] = su;
-                double sm = 0.0;
-#pragma unroll
-                for (int b = 0; b <= a; ++b)
-#pragma unroll
-                    for (int j = 0; j <= k; ++j) sm += w[1][b][j] * u[a - b][k - j];
-                mu[a][k] = sm;
-                p[a][k] = gm1 * (w[2][a][k] - 0.5 * sm);
-                ep[a][k] = w[2][a][k] + p[a][k];
-                double se = 0.0;
-#pragma unroll
-                for (int b = 0; b <= a; ++b)
-#pragma unroll
-                    for (int j = 0; j <= k; ++j) se += ep[b][j] * u[a - b][k - j];
-                epu[a][k] = se;
-            }
-#pragma unroll
-            for (int a = 0; a + k < 4; ++a) {
-                const double f = -(double)(a + 1) / (double)(k + 1);
-                w[0][a][k + 1] = f * w[1][a + 1][k];
-                w[1][a][k + 1] = f * (mu[a + 1][k] + p[a + 1][k]);
-                w[2][a][k + 1] = f * epu[a + 1][k];
-            }
-        }
-    }
-}
-
-// Steps 2-4 at one face: GRP from the two one-sided jets, then the flux of
-// eq. (flux) with the 4-point Gauss-Lobatto rule in time and the interface
-// state at t + dt (eq. (tay1d)).
-template <int EQ, int M>
-__device__ __forceinline__ void face1d(const double JL[5][M], const double JR[5][M],
-                                       double dt, const DevParams &P, double Fh[M],
-                                       double We[M])
-{
-    double w[M][5][5];
-    // leading term (sec. 2.1.1) and the derivative Riemann problems (eq. (lineq))
-    if constexpr (EQ == EULER) {
-        double Ws[M], R[M][M], L[M][M], lam[M];
-        hllc_state<1>(JL[0], JR[0], P.gamma, Ws);
-        euler_eigen<1, 0>(Ws, P.gamma, R, L, lam);
-        double scale = 0.0;
-#pragma unroll
-        for (int s = 0; s < M; ++s) scale = fmax(scale, fabs(lam[s]));
-#pragma unroll
-        for (int c = 0; c < M; ++c) w[c][0][0] = Ws[c];
-        const double inv_fact[5] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
-#pragma unroll
-        for (int a = 1; a < 5; ++a) {
-            double ch[M];
-#pragma unroll
-            for (int s = 0; s < M; ++s) {
-                double l = 0.0, r = 0.0;
-#pragma unroll
-                for (int c = 0; c < M; ++c) {
-                    l += L[s][c] * JL[a][c];
-                    r += L[s][c] * JR[a][c];
-                }
-                ch[s] = upwind(lam[s], scale, l, r);
-            }
-#pragma unroll
-            for (int c = 0; c < M; ++c) {
-                double d = 0.0;
-#pragma unroll
-                for (int s = 0; s < M; ++s) d += R[c][s] * ch[s];
-                w[c][a][0] = d * inv_fact[a];
-            }
-        }
-    } else {
-        double lam;
-        if constexpr (EQ == ADV) {
-            lam = P.adv_a;
-            w[0][0][0] = upwind(lam, fabs(lam), JL[0][0], JR[0][0]);
-        } else {
-            w[0][0][0] = burgers_state(JL[0][0], JR[0][0]);
-            lam = w[0][0][0];
-        }
-        const double inv_fact[5] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
-#pragma unroll
-        for (int a = 1; a < 5; ++a)
-            w[0][a][0] = upwind(lam, fabs(lam), JL[a][0], JR[a][0]) * inv_fact[a];
-    }
-    ck1d<EQ, M>(w, P);
-    // Gauss-Lobatto in time over [t_n, t_n + dt]
-    const double taus[4] = {0.0, (0.5 - LOB_H) * dt, (0.5 + LOB_H) * dt, dt};
-    const double wts[4] = {LOB_W0, LOB_W1, LOB_W1, LOB_W0};
-#pragma unroll
-    for (int c = 0; c < M; ++c) Fh[c] = 0.0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const double tau = taus[q];
-        double Wt[M], F[M];
-#pragma unroll
-        for (int c = 0; c < M; ++c)
-            Wt[c] = w[c][0][0] + tau * (w[c][0][1] + tau * (w[c][0][2] + tau * (w[c][0][3] + tau * w[c][0][4])));
-        phys_flux_x<EQ, 1>(Wt, P, F);
-#pragma unroll
-        for (int c = 0; c < M; ++c) Fh[c] += wts[q] * F[c];
-        if (q == 3) {
-#pragma unroll
-            for (int c = 0; c < M; ++c) We[c] = Wt[c];
-        }
-    }
-}
-
-template <int EQ>
-__device__ __forceinline__ double wave_speed(const double *W, const DevParams &P)
-{
-    if constexpr (EQ == ADV) return fabs(P.adv_a);
-    else if constexpr (EQ == BURG) return fabs(W[0]);
-    else {
-        const double u = W[1] / W[0];
-        const double p = (P.gamma - 1.0) * (W[2] - 0.5 * W[1] * u);
-        return fabs(u) + sqrt(P.gamma * p / W[0]);
-    }
-}
 
 template <int EQ>
 __device__ __forceinline__ bool bad_state(const double *W, const DevParams &P)
@@ -368,13 +136,12 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
             Wn[c] = __shfl_down(We[c], 1, WAVE);
         }
         if (lane >= 1 && lane <= CHUNK && j >= 0 && j < n) {
-            const double r = dt / d.dx, idx = 1.0 / d.dx;
-            double Wnew[M];
+            double Wnew[M], Vnew[M];
+            update1d<M>(W0, Fh, Fn, We, Wn, dt / d.dx, 1.0 / d.dx, Wnew, Vnew);
 #pragma unroll
             for (int c = 0; c < M; ++c) {
-                Wnew[c] = W0[c] - r * (Fn[c] - Fh[c]);
                 dst[c * n + j] = Wnew[c];
-                dst[(M + c) * n + j] = (Wn[c] - We[c]) * idx;
+                dst[(M + c) * n + j] = Vnew[c];
             }
             bad |= bad_state<EQ>(Wnew, P);
         }

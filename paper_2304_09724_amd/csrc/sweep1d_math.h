@@ -1,0 +1,255 @@
+// sweep1d_math.h -- per-cell and per-face arithmetic of the 1D sweep
+// (reconstruction, GRP, Gauss-Lobatto flux), templated on the real type.
+#pragma once
+
+#include "shw_math.h"
+
+namespace shw {
+
+// Step 1: reconstruction of one cell; lo/hi receive d^a W/dx^a at the left
+// and right edge, a = 0..4.
+template <int EQ, int M, class Re>
+SHW_HD void recon_cell(const Re Wm[M], const Re W0[M], const Re Wp[M], const Re Vm[M],
+                       const Re Vp[M], double dx, bool full, const DevParams &P,
+                       Re lo[5][M], Re hi[5][M])
+{
+    const double idx = 1.0 / dx;
+    double sc[5];
+    sc[0] = 1.0; sc[1] = idx; sc[2] = idx * idx; sc[3] = sc[2] * idx; sc[4] = sc[2] * sc[2];
+    if constexpr (EQ == EULER) {
+        if (full && P.charwise) {
+            Re R[M][M], L[M][M], lam[M];
+            euler_eigen<1, 0>(W0, P.gamma, R, L, lam);
+            Re clo[M][5], chi[M][5];
+#pragma unroll
+            for (int s = 0; s < M; ++s) {
+                Re am = 0.0, a0 = 0.0, ap = 0.0, bm = 0.0, bp = 0.0;
+#pragma unroll
+                for (int c = 0; c < M; ++c) {
+                    am += L[s][c] * Wm[c];
+                    a0 += L[s][c] * W0[c];
+                    ap += L[s][c] * Wp[c];
+                    bm += L[s][c] * Vm[c];
+                    bp += L[s][c] * Vp[c];
+                }
+                Re q[5], w[3];
+                big_quartic(am, a0, ap, Re(dx * bm), Re(dx * bp), q);
+                nonlinear_weights(q, am, a0, ap, P, w);
+                combine(q, am, a0, ap, w, P);
+                edge_derivs(q, clo[s], chi[s]);
+            }
+#pragma unroll
+            for (int a = 0; a < 5; ++a)
+#pragma unroll
+                for (int c = 0; c < M; ++c) {
+                    Re l = 0.0, h = 0.0;
+#pragma unroll
+                    for (int s = 0; s < M; ++s) {
+                        l += R[c][s] * clo[s][a];
+                        h += R[c][s] * chi[s][a];
+                    }
+                    lo[a][c] = l * sc[a];
+                    hi[a][c] = h * sc[a];
+                }
+            return;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        Re q[5], l5[5], h5[5];
+        big_quartic(Wm[c], W0[c], Wp[c], Re(dx * Vm[c]), Re(dx * Vp[c]), q);
+        if (full) {
+            Re w[3];
+            nonlinear_weights(q, Wm[c], W0[c], Wp[c], P, w);
+            combine(q, Wm[c], W0[c], Wp[c], w, P);
+        }
+        edge_derivs(q, l5, h5);
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            lo[a][c] = l5[a] * sc[a];
+            hi[a][c] = h5[a] * sc[a];
+        }
+    }
+}
+
+// Lax-Wendroff procedure (sec. 2.1.2, eq. (ck)) as power series in (x, t):
+// w[c][a][k] is the coefficient of x^a t^k; the PDE W_t = -F(W)_x gives
+// (k+1) w[a][k+1] = -(a+1) F[a+1][k].  Time level by time level, every series
+// coefficient of the fluxes is formed once (products by the Cauchy rule).
+template <int EQ, int M, class R>
+SHW_HD void ck1d(R w[M][5][5], const DevParams &P)
+{
+    if constexpr (EQ == ADV) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int a = 0; a + k < 4; ++a)
+                w[0][a][k + 1] = -P.adv_a * (double)(a + 1) / (double)(k + 1) * w[0][a + 1][k];
+    } else if constexpr (EQ == BURG) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int a = 0; a + k < 4; ++a) {
+                // F = W^2/2 at (a+1, k)
+                R s = 0.0;
+#pragma unroll
+                for (int b = 0; b <= a + 1; ++b)
+#pragma unroll
+                    for (int j = 0; j <= k; ++j) s += w[0][b][j] * w[0][a + 1 - b][k - j];
+                w[0][a][k + 1] = -0.5 * (double)(a + 1) / (double)(k + 1) * s;
+            }
+    } else {
+        const double gm1 = P.gamma - 1.0;
+        R r[5][5], u[5][5], mu[5][5], p[5][5], ep[5][5], epu[5][5];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+#pragma unroll
+            for (int a = 0; a + k <= 4; ++a) {
+                if (a == 0 && k == 0) {
+                    r[0][0] = 1.0 / w[0][0][0];
+                } else {
+                    R s = 0.0;
+#pragma unroll
+                    for (int b = 0; b <= a; ++b)
+#pragma unroll
+                        for (int j = 0; j <= k; ++j)
+                            if (b + j > 0) s += w[0][b][j] * r[a - b][k - j];
+                    r[a][k] = -s * r[0][0];
+                }
+                R su = 0.0;
+#pragma unroll
+                for (int b = 0; b <= a; ++b)
+#pragma unroll
+                    for (int j = 0; j <= k; ++j) su += w[1][b][j] * r[a - b][k - j];
+                u[a][k] = su;
+                R sm = 0.0;
+#pragma unroll
+                for (int b = 0; b <= a; ++b)
+#pragma unroll
+                    for (int j = 0; j <= k; ++j) sm += w[1][b][j] * u[a - b][k - j];
+                mu[a][k] = sm;
+                p[a][k] = gm1 * (w[2][a][k] - 0.5 * sm);
+                ep[a][k] = w[2][a][k] + p[a][k];
+                R se = 0.0;
+#pragma unroll
+                for (int b = 0; b <= a; ++b)
+#pragma unroll
+                    for (int j = 0; j <= k; ++j) se += ep[b][j] * u[a - b][k - j];
+                epu[a][k] = se;
+            }
+#pragma unroll
+            for (int a = 0; a + k < 4; ++a) {
+                const double f = -(double)(a + 1) / (double)(k + 1);
+                w[0][a][k + 1] = f * w[1][a + 1][k];
+                w[1][a][k + 1] = f * (mu[a + 1][k] + p[a + 1][k]);
+                w[2][a][k + 1] = f * epu[a + 1][k];
+            }
+        }
+    }
+}
+
+// Steps 2-4 at one face: GRP from the two one-sided jets, then the flux of
+// eq. (flux) with the 4-point Gauss-Lobatto rule in time and the interface
+// state at t + dt (eq. (tay1d)).
+template <int EQ, int M, class Re>
+SHW_HD void face1d(const Re JL[5][M], const Re JR[5][M], double dt, const DevParams &P,
+                   Re Fh[M], Re We[M])
+{
+    Re w[M][5][5];
+    // leading term (sec. 2.1.1) and the derivative Riemann problems (eq. (lineq))
+    if constexpr (EQ == EULER) {
+        Re Ws[M], R[M][M], L[M][M], lam[M];
+        hllc_state<1>(JL[0], JR[0], P.gamma, Ws);
+        euler_eigen<1, 0>(Ws, P.gamma, R, L, lam);
+        Re scale = 0.0;
+#pragma unroll
+        for (int s = 0; s < M; ++s) scale = fmax(scale, fabs(lam[s]));
+#pragma unroll
+        for (int c = 0; c < M; ++c) w[c][0][0] = Ws[c];
+        const double inv_fact[5] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
+#pragma unroll
+        for (int a = 1; a < 5; ++a) {
+            Re ch[M];
+#pragma unroll
+            for (int s = 0; s < M; ++s) {
+                Re l = 0.0, r = 0.0;
+#pragma unroll
+                for (int c = 0; c < M; ++c) {
+                    l += L[s][c] * JL[a][c];
+                    r += L[s][c] * JR[a][c];
+                }
+                ch[s] = upwind(lam[s], scale, l, r);
+            }
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                Re d = 0.0;
+#pragma unroll
+                for (int s = 0; s < M; ++s) d += R[c][s] * ch[s];
+                w[c][a][0] = d * inv_fact[a];
+            }
+        }
+    } else {
+        Re lam;
+        if constexpr (EQ == ADV) {
+            lam = P.adv_a;
+            w[0][0][0] = upwind(lam, Re(fabs(P.adv_a)), JL[0][0], JR[0][0]);
+        } else {
+            w[0][0][0] = burgers_state(JL[0][0], JR[0][0]);
+            lam = w[0][0][0];
+        }
+        const double inv_fact[5] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
+#pragma unroll
+        for (int a = 1; a < 5; ++a)
+            w[0][a][0] = upwind(lam, fabs(lam), JL[a][0], JR[a][0]) * inv_fact[a];
+    }
+    ck1d<EQ, M>(w, P);
+    // Gauss-Lobatto in time over [t_n, t_n + dt]
+    const double taus[4] = {0.0, (0.5 - LOB_H) * dt, (0.5 + LOB_H) * dt, dt};
+    const double wts[4] = {LOB_W0, LOB_W1, LOB_W1, LOB_W0};
+#pragma unroll
+    for (int c = 0; c < M; ++c) Fh[c] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double tau = taus[q];
+        Re Wt[M], F[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+            Wt[c] = w[c][0][0] + tau * (w[c][0][1] + tau * (w[c][0][2] + tau * (w[c][0][3] + tau * w[c][0][4])));
+        phys_flux_x<EQ, 1>(Wt, P, F);
+#pragma unroll
+        for (int c = 0; c < M; ++c) Fh[c] += wts[q] * F[c];
+        if (q == 3) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) We[c] = Wt[c];
+        }
+    }
+}
+
+
+// Largest characteristic speed of a cell average (CFL condition).
+template <int EQ, class R>
+SHW_HD R wave_speed(const R *W, const DevParams &P)
+{
+    if constexpr (EQ == ADV) return R(fabs(P.adv_a));
+    else if constexpr (EQ == BURG) return fabs(W[0]);
+    else {
+        const R u = W[1] / W[0];
+        const R p = (P.gamma - 1.0) * (W[2] - 0.5 * W[1] * u);
+        return fabs(u) + sqrt(P.gamma * p / W[0]);
+    }
+}
+
+// Step 5 for one cell: new average from the two face fluxes (eq. (cons)) and
+// new derivative average from the two interface states at t + dt (eq. (derave)).
+template <int M, class R>
+SHW_HD void update1d(const R W0[M], const R FL[M], const R FR[M], const R WL[M],
+                     const R WR[M], double dt_dx, double inv_dx, R Wn[M], R Vn[M])
+{
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        Wn[c] = W0[c] - dt_dx * (FR[c] - FL[c]);
+        Vn[c] = (WR[c] - WL[c]) * inv_dx;
+    }
+}
+
+} // namespace shw
