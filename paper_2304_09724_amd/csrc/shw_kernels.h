@@ -51,6 +51,33 @@ struct Loop1D {
     const uint8_t *flags;      // per cell gate flags (GATED mode)
 };
 
+// Launch parameters of one 2D step over a batch (all pointers device-side).
+struct Step2D {
+    const Inst2D *inst;
+    int n_inst;
+    const int *tile_off[2];    // per sweep direction: first tile of each instance (n_inst+1)
+    double *state;             // caller's state buffer
+    double *alt;               // ping-pong buffer
+    int *parity;               // per instance: 1 = current state is in alt
+    double *dt;                // per instance step of the current step (0 = skip)
+    int *last;                 // per instance: the step ends exactly at t_end
+    const double *dt_fixed;    // per instance fixed step (fixed-step mode)
+    const double *t_end;       // per instance end time (CFL mode)
+    long long *steps_left;     // per instance step budget
+    double *smax;              // per instance max of (|u|+c)/dx + (|v|+c)/dy
+    int *bad;                  // per instance sticky non-physical flag
+    int *active;               // instances still running after the last step
+    InstState *ist;
+    const uint8_t *flags;      // per cell gate flags (GATED mode)
+};
+
+int sweep2d_tiles(int n_sweep, int n_trans);
+hipError_t launch_speed2d(int eq, const Step2D &S, const DevParams &P, int use_parity,
+                          hipStream_t stream);
+hipError_t launch_step2d(int eq, const Step2D &S, const DevParams &P, int fixed,
+                         const int total_tiles[2], hipStream_t stream);
+hipError_t launch_settle2d(const Step2D &S, int m, hipStream_t stream);
+
 hipError_t launch_loop1d(int eq, const Loop1D &L, const DevParams &P, int grid,
                          hipStream_t stream);
 int loop1d_max_blocks(int eq);

@@ -59,7 +59,8 @@ size_t state_doubles(const shw_mesh *m, int eq)
 // Device workspace carved out of the caller's buffer.
 struct Layout {
     size_t alt = 0, inst = 0, order = 0, queue = 0, ist = 0, t_end = 0, dt = 0,
-           flags = 0, total = 0;
+           flags = 0, tiles0 = 0, tiles1 = 0, parity = 0, last = 0, dt_fixed = 0,
+           steps_left = 0, smax = 0, bad = 0, active = 0, total = 0;
 };
 
 Layout make_layout(const shw_mesh *meshes, int n_inst, const shw_params *p)
@@ -80,6 +81,15 @@ Layout make_layout(const shw_mesh *meshes, int n_inst, const shw_params *p)
     L.t_end = take((size_t)n_inst * sizeof(double));
     L.dt = take((size_t)n_inst * sizeof(double));
     L.flags = take(cells);
+    L.tiles0 = take((size_t)(n_inst + 1) * sizeof(int));
+    L.tiles1 = take((size_t)(n_inst + 1) * sizeof(int));
+    L.parity = take((size_t)n_inst * sizeof(int));
+    L.last = take((size_t)n_inst * sizeof(int));
+    L.dt_fixed = take((size_t)n_inst * sizeof(double));
+    L.steps_left = take((size_t)n_inst * sizeof(long long));
+    L.smax = take((size_t)n_inst * sizeof(double));
+    L.bad = take((size_t)n_inst * sizeof(int));
+    L.active = take(256);
     L.total = off;
     return L;
 }
@@ -97,6 +107,7 @@ struct shw_ctx {
     Layout lay;
     hipStream_t stream = nullptr;
     int grid1d = 1;
+    int tiles2d[2] = {0, 0};
     int bad_instance = -1;
     std::string msg;
 
@@ -166,6 +177,8 @@ shw_status shw_create(const shw_mesh *meshes, int n_inst, const shw_params *para
 
     long long o = 0, co = 0;
     std::vector<Inst1D> i1;
+    std::vector<Inst2D> i2;
+    std::vector<int> toff0(1, 0), toff1(1, 0);
     for (int i = 0; i < n_inst; ++i) {
         const shw_mesh &m = meshes[i];
         c->off.push_back(o);
@@ -179,6 +192,18 @@ shw_status shw_create(const shw_mesh *meshes, int n_inst, const shw_params *para
             d.bc_hi = m.bc[1];
             d.dx = (m.x1 - m.x0) / m.nx;
             i1.push_back(d);
+        } else {
+            Inst2D d{};
+            d.off = o;
+            d.cell_off = co;
+            d.nx = m.nx;
+            d.ny = m.ny;
+            for (int k = 0; k < 4; ++k) d.bc[k] = m.bc[k];
+            d.dx = (m.x1 - m.x0) / m.nx;
+            d.dy = (m.y1 - m.y0) / m.ny;
+            i2.push_back(d);
+            toff0.push_back(toff0.back() + sweep2d_tiles(m.nx, m.ny));
+            toff1.push_back(toff1.back() + sweep2d_tiles(m.ny, m.nx));
         }
         o += (long long)state_doubles(&m, params->eq);
         co += (long long)m.nx * m.ny;
@@ -195,7 +220,24 @@ shw_status shw_create(const shw_mesh *meshes, int n_inst, const shw_params *para
         s = c->hip(hipMemcpyAsync(c->ws + c->lay.inst, i1.data(), i1.size() * sizeof(Inst1D),
                                   hipMemcpyHostToDevice, c->stream), "copy instances");
         c->grid1d = loop1d_max_blocks(params->eq);
+    } else {
+        s = c->hip(hipMemcpyAsync(c->ws + c->lay.inst, i2.data(), i2.size() * sizeof(Inst2D),
+                                  hipMemcpyHostToDevice, c->stream), "copy instances");
+        if (s == SHW_OK)
+            s = c->hip(hipMemcpyAsync(c->ws + c->lay.tiles0, toff0.data(), toff0.size() * sizeof(int),
+                                      hipMemcpyHostToDevice, c->stream), "copy tiles");
+        if (s == SHW_OK)
+            s = c->hip(hipMemcpyAsync(c->ws + c->lay.tiles1, toff1.data(), toff1.size() * sizeof(int),
+                                      hipMemcpyHostToDevice, c->stream), "copy tiles");
+        c->tiles2d[0] = toff0.back();
+        c->tiles2d[1] = toff1.back();
     }
+    if (s == SHW_OK)
+        s = c->hip(hipMemsetAsync(c->ws + c->lay.parity, 0, n_inst * sizeof(int), c->stream),
+                   "clear parity");
+    if (s == SHW_OK)
+        s = c->hip(hipMemsetAsync(c->ws + c->lay.bad, 0, n_inst * sizeof(int), c->stream),
+                   "clear flags");
     if (s == SHW_OK)
         s = c->hip(hipMemcpyAsync(c->ws + c->lay.order, order.data(), n_inst * sizeof(int),
                                   hipMemcpyHostToDevice, c->stream), "copy order");
@@ -226,6 +268,9 @@ shw_status shw_set_state(shw_ctx *c, int inst, const double *src, int on_device)
     // clear the sticky non-physical flag of this instance
     s = c->hip(hipMemsetAsync(reinterpret_cast<char *>(c->ist() + inst) + offsetof(InstState, code),
                               0, sizeof(int), c->stream), "set_state flag");
+    if (s != SHW_OK) return s;
+    s = c->hip(hipMemsetAsync(c->ws + c->lay.bad + inst * sizeof(int), 0, sizeof(int), c->stream),
+               "set_state flag");
     if (s != SHW_OK) return s;
     if (!on_device) return c->hip(hipStreamSynchronize(c->stream), "set_state sync");
     return SHW_OK;
@@ -287,6 +332,8 @@ shw_status shw_set_time(shw_ctx *c, const double *t)
     return c->hip(hipStreamSynchronize(c->stream), "set_time sync");
 }
 
+static Step2D step2d_args(shw_ctx *c);
+
 shw_status shw_compute_dt(shw_ctx *c, double *dt)
 {
     if (!c || !dt) return SHW_EINVAL;
@@ -296,20 +343,58 @@ shw_status shw_compute_dt(shw_ctx *c, double *dt)
         s = c->hip(launch_dt1d(c->params.eq, c->at<Inst1D>(c->lay.inst), c->n_inst, c->state,
                                c->dp, d_dt, c->stream), "dt1d");
     } else {
-        return c->fail(SHW_ESTATE, "2D not built yet");
+        Step2D S = step2d_args(c);
+        s = c->hip(launch_speed2d(c->params.eq, S, c->dp, 0, c->stream), "speed2d");
+        if (s != SHW_OK) return s;
+        std::vector<double> smax(c->n_inst);
+        std::vector<int> bad(c->n_inst);
+        s = c->hip(hipMemcpyAsync(smax.data(), S.smax, c->n_inst * sizeof(double),
+                                  hipMemcpyDeviceToHost, c->stream), "smax copy");
+        if (s == SHW_OK)
+            s = c->hip(hipMemcpyAsync(bad.data(), S.bad, c->n_inst * sizeof(int),
+                                      hipMemcpyDeviceToHost, c->stream), "bad copy");
+        if (s == SHW_OK) s = c->hip(hipStreamSynchronize(c->stream), "dt sync");
+        if (s != SHW_OK) return s;
+        for (int i = 0; i < c->n_inst; ++i)
+            dt[i] = bad[i] ? -1.0 : c->params.cfl / smax[i];
     }
-    if (s != SHW_OK) return s;
-    s = c->hip(hipMemcpyAsync(dt, d_dt, c->n_inst * sizeof(double), hipMemcpyDeviceToHost,
-                              c->stream), "dt copy");
-    if (s != SHW_OK) return s;
-    s = c->hip(hipStreamSynchronize(c->stream), "dt sync");
-    if (s != SHW_OK) return s;
+    if (c->dim == 1) {
+        if (s != SHW_OK) return s;
+        s = c->hip(hipMemcpyAsync(dt, d_dt, c->n_inst * sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream), "dt copy");
+        if (s != SHW_OK) return s;
+        s = c->hip(hipStreamSynchronize(c->stream), "dt sync");
+        if (s != SHW_OK) return s;
+    }
     for (int i = 0; i < c->n_inst; ++i)
         if (!(dt[i] > 0.0)) {
             c->bad_instance = i;
             return c->fail(SHW_ENONPHYS, "non-physical cell average");
         }
     return SHW_OK;
+}
+
+static Step2D step2d_args(shw_ctx *c)
+{
+    Step2D S{};
+    S.inst = c->at<Inst2D>(c->lay.inst);
+    S.n_inst = c->n_inst;
+    S.tile_off[0] = c->at<int>(c->lay.tiles0);
+    S.tile_off[1] = c->at<int>(c->lay.tiles1);
+    S.state = c->state;
+    S.alt = c->alt();
+    S.parity = c->at<int>(c->lay.parity);
+    S.dt = c->at<double>(c->lay.dt);
+    S.last = c->at<int>(c->lay.last);
+    S.dt_fixed = c->at<double>(c->lay.dt_fixed);
+    S.t_end = c->at<double>(c->lay.t_end);
+    S.steps_left = c->at<long long>(c->lay.steps_left);
+    S.smax = c->at<double>(c->lay.smax);
+    S.bad = c->at<int>(c->lay.bad);
+    S.active = c->at<int>(c->lay.active);
+    S.ist = c->ist();
+    S.flags = c->at<uint8_t>(c->lay.flags);
+    return S;
 }
 
 static Loop1D loop_args(shw_ctx *c)
@@ -331,17 +416,55 @@ shw_status shw_step(shw_ctx *c, const double *dt)
     if (!c || !dt) return SHW_EINVAL;
     for (int i = 0; i < c->n_inst; ++i)
         if (!std::isfinite(dt[i])) return SHW_EINVAL;
+    if (c->dim == 2) {
+        Step2D S = step2d_args(c);
+        shw_status s = c->hip(hipMemcpyAsync(const_cast<double *>(S.dt_fixed), dt,
+                                             c->n_inst * sizeof(double), hipMemcpyHostToDevice,
+                                             c->stream), "step dt");
+        if (s != SHW_OK) return s;
+        s = c->hip(launch_step2d(c->params.eq, S, c->dp, 1, c->tiles2d, c->stream), "step2d");
+        if (s != SHW_OK) return s;
+        return c->hip(launch_settle2d(S, c->m, c->stream), "settle");
+    }
     double *d_dt = c->at<double>(c->lay.dt);
     shw_status s = c->hip(hipMemcpyAsync(d_dt, dt, c->n_inst * sizeof(double),
                                          hipMemcpyHostToDevice, c->stream), "step dt");
     if (s != SHW_OK) return s;
-    if (c->dim != 1) return c->fail(SHW_ESTATE, "2D not built yet");
     Loop1D L = loop_args(c);
     L.dt_fixed = d_dt;
     L.t_end = nullptr;
     L.max_steps = 1;
     int grid = std::min(c->grid1d, c->n_inst);
     return c->hip(launch_loop1d(c->params.eq, L, c->dp, grid, c->stream), "step");
+}
+
+// 2D time loop: steps run on the device in chunks; the host only polls the
+// number of instances still running between chunks.
+static shw_status advance2d(shw_ctx *c, long long max_steps)
+{
+    constexpr int CHUNK_STEPS = 8;
+    Step2D S = step2d_args(c);
+    std::vector<long long> budget(c->n_inst, max_steps);
+    shw_status s = c->hip(hipMemcpyAsync(S.steps_left, budget.data(), c->n_inst * sizeof(long long),
+                                         hipMemcpyHostToDevice, c->stream), "budget");
+    if (s != SHW_OK) return s;
+    s = c->hip(launch_speed2d(c->params.eq, S, c->dp, 1, c->stream), "speed2d");
+    if (s != SHW_OK) return s;
+    for (long long done = 0; done < max_steps;) {
+        const int k = (int)std::min<long long>(CHUNK_STEPS, max_steps - done);
+        for (int j = 0; j < k; ++j) {
+            s = c->hip(launch_step2d(c->params.eq, S, c->dp, 0, c->tiles2d, c->stream), "step2d");
+            if (s != SHW_OK) return s;
+        }
+        done += k;
+        int active = 0;
+        s = c->hip(hipMemcpyAsync(&active, S.active, sizeof(int), hipMemcpyDeviceToHost, c->stream),
+                   "active");
+        if (s == SHW_OK) s = c->hip(hipStreamSynchronize(c->stream), "active sync");
+        if (s != SHW_OK) return s;
+        if (active == 0) break;
+    }
+    return c->hip(launch_settle2d(S, c->m, c->stream), "settle");
 }
 
 shw_status shw_advance_to(shw_ctx *c, const double *T, long long max_steps, long long *steps_out)
@@ -356,7 +479,10 @@ shw_status shw_advance_to(shw_ctx *c, const double *T, long long max_steps, long
     s = c->hip(hipMemcpyAsync(d_T, T, c->n_inst * sizeof(double), hipMemcpyHostToDevice,
                               c->stream), "advance T");
     if (s != SHW_OK) return s;
-    if (c->dim != 1) return c->fail(SHW_ESTATE, "2D not built yet");
+    if (c->dim == 2) {
+        s = advance2d(c, max_steps);
+        if (s != SHW_OK) return s;
+    } else {
     Loop1D L = loop_args(c);
     L.dt_fixed = nullptr;
     L.t_end = d_T;
@@ -364,6 +490,7 @@ shw_status shw_advance_to(shw_ctx *c, const double *T, long long max_steps, long
     int grid = std::min(c->grid1d, c->n_inst);
     s = c->hip(launch_loop1d(c->params.eq, L, c->dp, grid, c->stream), "advance");
     if (s != SHW_OK) return s;
+    }
     std::vector<InstState> after;
     s = read_ist(c, after);
     if (s != SHW_OK) return s;

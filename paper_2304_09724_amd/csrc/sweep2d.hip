@@ -1,0 +1,451 @@
+// sweep2d.hip -- one 2D ADER-SHWENO time step for a batch of rectangles:
+// an x-sweep and a y-sweep kernel (unsplit: both read the state at t_n), the
+// CFL reduction, and the small kernels that run the per-instance time loop on
+// the device (step size, time, ping-pong parity, done and non-physical
+// flags), so a sequence of steps can be replayed as one HIP graph.
+//
+// A sweep kernel works on tiles of 4 lines x 60 cells: one wave per line
+// (a row for the x-sweep, a column for the y-sweep), one lane per cell.  Lane
+// l holds cell c0 + l - 2.  Every lane does stage 1 of its cell (transverse
+// reconstruction, sec. 3.2); lanes 1..62 do stage 2 at each of the four
+// Gauss-Lobatto edge nodes, getting the neighbours' stage-1 node values by
+// wave shuffles; lanes 2..62 solve the GRP at their cell's lower interface
+// node by node (sec. 3.1) and accumulate the flux of eq. (fx2d); lanes 2..61
+// update their cell (sec. 3, the 2D form of eq. (cons), eqs. (derave2d)).
+// The y-sweep runs the same code on the state seen with x and y exchanged.
+#include "shw_kernels.h"
+#include "sweep2d_math.h"
+
+namespace shw {
+
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;
+constexpr int LINES = BLOCK / WAVE;
+constexpr int CHUNK = WAVE - 4;
+
+// source index of a (possibly ghost) index j of an axis of n cells
+__device__ __forceinline__ int map_index(int j, int n, int bc_lo, int bc_hi, int &kind)
+{
+    kind = -1;
+    if (j >= 0 && j < n) return j;
+    kind = j < 0 ? bc_lo : bc_hi;
+    if (kind == BC_PERIODIC) return j < 0 ? j + n : j - n;
+    if (kind == BC_TRANSMISSIVE) return j < 0 ? 0 : n - 1;
+    return j < 0 ? -1 - j : 2 * n - 1 - j;
+}
+
+// The four averages of the cell at sweep index s, transverse index t, seen in
+// the frame of sweep direction DIR (for DIR = 1: x <-> y, V <-> Y, momenta
+// swapped).  Ghost cells by the boundary conditions of each axis: periodic
+// wrap; transmissive copies with every average containing the normal
+// derivative set to zero; reflective mirrors with odd quantities negated.
+template <int EQ, int M, int DIR>
+__device__ __forceinline__ long long load_cell2d(const double *__restrict__ base, const Inst2D &d,
+                                                 int s, int t, double W[M], double V[M],
+                                                 double Y[M], double Z[M])
+{
+    const int i = DIR == 0 ? s : t, j = DIR == 0 ? t : s;
+    int kx, ky;
+    const int si = map_index(i, d.nx, d.bc[0], d.bc[1], kx);
+    const int sj = map_index(j, d.ny, d.bc[2], d.bc[3], ky);
+    const long long plane = (long long)d.nx * d.ny;
+    const long long o = (long long)sj * d.nx + si;
+    double q[4][M];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int c = 0; c < M; ++c) q[k][c] = base[(k * M + c) * plane + o];
+    if (kx == BC_TRANSMISSIVE) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) { q[1][c] = 0.0; q[3][c] = 0.0; }
+    } else if (kx == BC_REFLECTIVE) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            const double par = (EQ == EULER && c == 1) ? -1.0 : 1.0;
+            q[0][c] *= par; q[1][c] *= -par; q[2][c] *= par; q[3][c] *= -par;
+        }
+    }
+    if (ky == BC_TRANSMISSIVE) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) { q[2][c] = 0.0; q[3][c] = 0.0; }
+    } else if (ky == BC_REFLECTIVE) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            const double par = (EQ == EULER && c == 2) ? -1.0 : 1.0;
+            q[0][c] *= par; q[1][c] *= par; q[2][c] *= -par; q[3][c] *= -par;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        const int cc = (DIR == 1 && EQ == EULER && (c == 1 || c == 2)) ? 3 - c : c;
+        W[c] = q[0][cc];
+        V[c] = DIR == 0 ? q[1][cc] : q[2][cc];
+        Y[c] = DIR == 0 ? q[2][cc] : q[1][cc];
+        Z[c] = q[3][cc];
+    }
+    return o;
+}
+
+__device__ __forceinline__ int find_instance(const int *__restrict__ off, int n, int b)
+{
+    int lo = 0, hi = n;          // off[lo] <= b < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <int EQ, int DIR>
+__global__ void __launch_bounds__(BLOCK) sweep2d_kernel(Step2D S, DevParams P)
+{
+    constexpr int M = NComp<EQ, 2>::M;
+    const int inst = find_instance(S.tile_off[DIR], S.n_inst, blockIdx.x);
+    const double dt = S.dt[inst];
+    if (!(dt > 0.0)) return;
+    const Inst2D d = S.inst[inst];
+    const int ns = DIR == 0 ? d.nx : d.ny, nt = DIR == 0 ? d.ny : d.nx;
+    const double dS = DIR == 0 ? d.dx : d.dy, dT = DIR == 0 ? d.dy : d.dx;
+    const double as = DIR == 0 ? P.adv_a : P.adv_b, at = DIR == 0 ? P.adv_b : P.adv_a;
+    const int tiles_s = (ns + CHUNK - 1) / CHUNK;
+    const int tile = blockIdx.x - S.tile_off[DIR][inst];
+    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+    const int t = (tile / tiles_s) * LINES + wave;
+    if (t >= nt) return;
+    const int s = (tile % tiles_s) * CHUNK + lane - 2;
+    const bool live = s <= ns + 1;
+    const int par = S.parity[inst];
+    const double *src = (par ? S.alt : S.state) + d.off;
+    double *dst = (par ? S.state : S.alt) + d.off;
+
+    // ---- stage 1 of this lane's cell -------------------------------------
+    // The stage-1 polynomials are parked in LDS for the node loop: a 256-lane
+    // block of this kernel fills a CU's register file on its own, so the LDS
+    // is free; the layout [coefficient][lane] keeps accesses conflict-free.
+    __shared__ double s_poly[2][M][5][BLOCK];
+    double Wc[M];
+    bool full = P.weights == W_NONLINEAR;
+    {
+        double PW[M][5], PV[M][5];
+        if (live) {
+            double W[3][M], V[3][M], Y[3][M], Z[3][M];
+            long long o = 0;
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const long long ol = load_cell2d<EQ, M, DIR>(src, d, s, t - 1 + l, W[l], V[l], Y[l], Z[l]);
+                if (l == 1) o = ol;
+            }
+            if (P.weights == W_GATED) full = S.flags[d.cell_off + o] != 0;
+            stage1<M, EQ>(W, V, Y, Z, dT, full, P, PW, PV);
+#pragma unroll
+            for (int c = 0; c < M; ++c) Wc[c] = W[1][c];
+        } else {
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                Wc[c] = 1.0;
+#pragma unroll
+                for (int k = 0; k < 5; ++k) { PW[c][k] = 0.0; PV[c][k] = 0.0; }
+            }
+            Wc[M - 1] = 3.0;
+        }
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                s_poly[0][c][k][threadIdx.x] = PW[c][k];
+                s_poly[1][c][k][threadIdx.x] = PV[c][k];
+            }
+    }
+    const double iT = 1.0 / dT, iS = 1.0 / dS;
+    const double sct[5] = {1.0, iT, iT * iT, iT * iT * iT, iT * iT * iT * iT};
+    const double scs[5] = {1.0, iS, iS * iS, iS * iS * iS, iS * iS * iS * iS};
+    const double node[4] = {-0.5, -LOB_H, LOB_H, 0.5};
+    const double nw[4] = {LOB_W0, LOB_W1, LOB_W1, LOB_W0};
+
+    double Fh[M], We[4][M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) Fh[c] = 0.0;
+    const bool face = lane >= 2 && lane <= 62 && s >= 0 && s <= ns;
+#pragma unroll 1
+    for (int g = 0; g < 4; ++g) {
+        // characteristic fields of the sweep Jacobian at the cell average
+        double Lm[M][M], Rm[M][M];
+        if constexpr (EQ == EULER) {
+            double lam[M];
+            euler_eigen<2, 0>(Wc, P.gamma, Rm, Lm, lam);
+        } else {
+            Lm[0][0] = 1.0; Rm[0][0] = 1.0;
+        }
+        // Stage 2 order by order; each order's jets move to the lane above at
+        // once and become the GRP's series seeds there, so only one order of
+        // jets is ever held (each lane reads back only its own LDS slots).
+        const double inv_fact[5] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
+        double w[M][3], seed[M][5][5];
+        Leading2D<M, EQ, double> G;
+#pragma unroll
+        for (int n = 0; n <= 4; ++n) {
+            double am[M], a0[M], ap[M], bm[M], bp[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                // volatile: re-read per order rather than held in registers
+                const volatile double *vp = &s_poly[0][0][0][0];
+                double pw[5], pv[5];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    pw[k] = vp[((0 * M + c) * 5 + k) * BLOCK + threadIdx.x];
+                    pv[k] = vp[((1 * M + c) * 5 + k) * BLOCK + threadIdx.x];
+                }
+                const double A = deriv_at(pw, node[g], n, sct[n]);
+                const double B = deriv_at(pv, node[g], n, sct[n]);
+                a0[c] = A;
+                am[c] = __shfl_up(A, 1, WAVE);
+                ap[c] = __shfl_down(A, 1, WAVE);
+                bm[c] = __shfl_up(B, 1, WAVE);
+                bp[c] = __shfl_down(B, 1, WAVE);
+            }
+            double lo[5][M], hi[5][M];
+            if (lane >= 1 && lane <= 62 && live) {
+                stage2_order<M, EQ>(n, am, a0, ap, bm, bp, Lm, Rm, dS, scs, full, P, w, lo, hi);
+            } else {
+#pragma unroll
+                for (int a = 0; a < 5; ++a)
+#pragma unroll
+                    for (int c = 0; c < M; ++c) { lo[a][c] = 0.0; hi[a][c] = 0.0; }
+            }
+#pragma unroll
+            for (int a = 0; a + n <= 4; ++a) {
+                double JL[M];
+#pragma unroll
+                for (int c = 0; c < M; ++c) JL[c] = __shfl_up(hi[a][c], 1, WAVE);
+                if (face) {
+                    if (a + n == 0) {
+                        grp2d_leading<M, EQ>(JL, lo[0], P, as, G);
+#pragma unroll
+                        for (int c = 0; c < M; ++c) seed[c][0][0] = G.Ws[c];
+                    } else {
+                        double o[M];
+                        grp2d_seed<M, EQ>(JL, lo[a], G, inv_fact[a] * inv_fact[n], o);
+#pragma unroll
+                        for (int c = 0; c < M; ++c) seed[c][a][n] = o[c];
+                    }
+                }
+            }
+        }
+        if (face) {
+            double wt[M][5], Fg[M], Wg[M];
+            if constexpr (EQ == EULER) ck2d_euler(seed, P.gamma, wt);
+            else ck2d_adv(seed[0], as, at, wt[0]);
+            node_flux<M, EQ>(wt, dt, P, as, Fg, Wg);
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                Fh[c] += nw[g] * Fg[c];
+                We[g][c] = Wg[c];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < M; ++c) We[g][c] = 0.0;
+        }
+    }
+    // ---- update (this lane's cell; upper interface from lane + 1) ----------
+    double Fu[M], Wu[4][M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        Fu[c] = __shfl_down(Fh[c], 1, WAVE);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) Wu[g][c] = __shfl_down(We[g][c], 1, WAVE);
+    }
+    if (!(lane >= 2 && lane <= 61 && s >= 0 && s < ns)) return;
+    const int i = DIR == 0 ? s : t, j = DIR == 0 ? t : s;
+    const long long plane = (long long)d.nx * d.ny;
+    const long long o = (long long)j * d.nx + i;
+    const double r = dt / dS, iSS = 1.0 / (d.dx * d.dy);
+    double Wn[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        const int cc = (DIR == 1 && EQ == EULER && (c == 1 || c == 2)) ? 3 - c : c;
+        double dv = 0.0;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) dv += nw[g] * (Wu[g][c] - We[g][c]);
+        const double zc = 0.5 * (Wu[3][c] - We[3][c] - Wu[0][c] + We[0][c]) * iSS;
+        if constexpr (DIR == 0) {
+            Wn[cc] = src[cc * plane + o] - r * (Fu[c] - Fh[c]);
+            dst[cc * plane + o] = Wn[cc];
+            dst[(M + cc) * plane + o] = dv * iS;
+            dst[(3 * M + cc) * plane + o] = zc;
+        } else {
+            Wn[cc] = dst[cc * plane + o] - r * (Fu[c] - Fh[c]);
+            dst[cc * plane + o] = Wn[cc];
+            dst[(2 * M + cc) * plane + o] = dv * iS;
+            dst[(3 * M + cc) * plane + o] += zc;
+        }
+    }
+    if constexpr (DIR == 1) {
+        // non-physical check and the wave speed for the next step's CFL
+        bool bad = false;
+#pragma unroll
+        for (int c = 0; c < M; ++c) bad |= !isfinite(Wn[c]);
+        double spd = 0.0;
+        if constexpr (EQ == EULER) {
+            const double ir = 1.0 / Wn[0];
+            const double u = Wn[1] * ir, v = Wn[2] * ir;
+            const double p = (P.gamma - 1.0) * (Wn[3] - 0.5 * Wn[0] * (u * u + v * v));
+            bad |= !(Wn[0] > 0.0) || !(p > 0.0);
+            if (!bad) {
+                const double c = sqrt(P.gamma * p * ir);
+                spd = (fabs(u) + c) / d.dx + (fabs(v) + c) / d.dy;
+            }
+        } else {
+            spd = fabs(P.adv_a) / d.dx + fabs(P.adv_b) / d.dy;
+        }
+        if (bad) atomicOr(&S.bad[inst], 1);
+        // positive doubles order like their bit patterns
+        atomicMax(reinterpret_cast<unsigned long long *>(&S.smax[inst]),
+                  (unsigned long long)__double_as_longlong(spd));
+    }
+}
+
+// max over the cells of (|u|+c)/dx + (|v|+c)/dy, one block per instance
+template <int EQ>
+__global__ void __launch_bounds__(BLOCK) speed2d_kernel(Step2D S, DevParams P, int use_parity)
+{
+    constexpr int M = NComp<EQ, 2>::M;
+    __shared__ double red[LINES];
+    const int inst = blockIdx.x;
+    const Inst2D d = S.inst[inst];
+    const double *src = ((use_parity && S.parity[inst]) ? S.alt : S.state) + d.off;
+    const long long plane = (long long)d.nx * d.ny;
+    double m = 0.0;
+    bool bad = false;
+    for (long long o = threadIdx.x; o < plane; o += BLOCK) {
+        double W[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) W[c] = src[c * plane + o];
+        if constexpr (EQ == EULER) {
+            const double ir = 1.0 / W[0];
+            const double u = W[1] * ir, v = W[2] * ir;
+            const double p = (P.gamma - 1.0) * (W[3] - 0.5 * W[0] * (u * u + v * v));
+            const bool b = !isfinite(W[0]) || !isfinite(W[1]) || !isfinite(W[2]) ||
+                           !isfinite(W[3]) || !(W[0] > 0.0) || !(p > 0.0);
+            bad |= b;
+            if (!b) {
+                const double c = sqrt(P.gamma * p * ir);
+                m = fmax(m, (fabs(u) + c) / d.dx + (fabs(v) + c) / d.dy);
+            }
+        } else {
+            bad |= !isfinite(W[0]);
+            m = fmax(m, fabs(P.adv_a) / d.dx + fabs(P.adv_b) / d.dy);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, WAVE));
+    if (threadIdx.x % WAVE == 0) red[threadIdx.x / WAVE] = m;
+    const int any_bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0) {
+        double r = red[0];
+        for (int w = 1; w < LINES; ++w) r = fmax(r, red[w]);
+        S.smax[inst] = r;
+        if (any_bad) S.bad[inst] = 1;
+    }
+}
+
+// per instance, before a step: dt from the CFL condition (or the fixed dt),
+// clamped to the end time; 0 for instances that are done or non-physical
+__global__ void prepare2d_kernel(Step2D S, DevParams P, int fixed)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *S.active = 0;
+    if (i >= S.n_inst) return;
+    InstState st = S.ist[i];
+    double dt = 0.0;
+    int last = 0;
+    if (S.bad[i] != 0 || st.code != 0) {
+        st.code = 1;
+    } else if (fixed) {
+        dt = S.dt_fixed[i] > 0.0 ? S.dt_fixed[i] : 0.0;
+    } else if (st.t < S.t_end[i] && S.steps_left[i] > 0) {
+        dt = P.cfl / S.smax[i];
+        if (dt >= S.t_end[i] - st.t) { dt = S.t_end[i] - st.t; last = 1; }
+    }
+    S.dt[i] = dt;
+    S.last[i] = last;
+    S.smax[i] = 0.0;
+    S.ist[i] = st;
+}
+
+// per instance, after a step: time, step count, parity, budget, activity
+__global__ void finish2d_kernel(Step2D S)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.n_inst) return;
+    const double dt = S.dt[i];
+    if (!(dt > 0.0)) return;
+    InstState st = S.ist[i];
+    st.t = S.last[i] ? S.t_end[i] : st.t + dt;
+    st.steps += 1;
+    if (S.bad[i] != 0) st.code = 1;
+    S.ist[i] = st;
+    S.parity[i] ^= 1;
+    S.steps_left[i] -= 1;
+    if (st.code == 0 && st.t < S.t_end[i] && S.steps_left[i] > 0) atomicAdd(S.active, 1);
+}
+
+// copy instances whose current state sits in the ping-pong buffer back to
+// the caller's buffer (one block per instance)
+__global__ void settle2d_kernel(Step2D S, int m)
+{
+    const int inst = blockIdx.y;
+    if (S.parity[inst] == 0) return;
+    const Inst2D d = S.inst[inst];
+    const long long n = 4LL * m * d.nx * d.ny;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (long long)gridDim.x * blockDim.x)
+        S.state[d.off + e] = S.alt[d.off + e];
+}
+
+__global__ void clear_parity2d_kernel(Step2D S)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < S.n_inst) S.parity[i] = 0;
+}
+
+} // namespace
+
+int sweep2d_tiles(int n_sweep, int n_trans)
+{
+    return ((n_sweep + CHUNK - 1) / CHUNK) * ((n_trans + LINES - 1) / LINES);
+}
+
+hipError_t launch_speed2d(int eq, const Step2D &S, const DevParams &P, int use_parity,
+                          hipStream_t st)
+{
+    if (eq == EULER) speed2d_kernel<EULER><<<S.n_inst, BLOCK, 0, st>>>(S, P, use_parity);
+    else speed2d_kernel<ADV><<<S.n_inst, BLOCK, 0, st>>>(S, P, use_parity);
+    return hipGetLastError();
+}
+
+hipError_t launch_step2d(int eq, const Step2D &S, const DevParams &P, int fixed,
+                         const int total_tiles[2], hipStream_t st)
+{
+    const int nb = (S.n_inst + 255) / 256;
+    prepare2d_kernel<<<nb, 256, 0, st>>>(S, P, fixed);
+    if (eq == EULER) {
+        sweep2d_kernel<EULER, 0><<<total_tiles[0], BLOCK, 0, st>>>(S, P);
+        sweep2d_kernel<EULER, 1><<<total_tiles[1], BLOCK, 0, st>>>(S, P);
+    } else {
+        sweep2d_kernel<ADV, 0><<<total_tiles[0], BLOCK, 0, st>>>(S, P);
+        sweep2d_kernel<ADV, 1><<<total_tiles[1], BLOCK, 0, st>>>(S, P);
+    }
+    finish2d_kernel<<<nb, 256, 0, st>>>(S);
+    return hipGetLastError();
+}
+
+hipError_t launch_settle2d(const Step2D &S, int m, hipStream_t st)
+{
+    settle2d_kernel<<<dim3(64, S.n_inst), 256, 0, st>>>(S, m);
+    clear_parity2d_kernel<<<(S.n_inst + 255) / 256, 256, 0, st>>>(S);
+    return hipGetLastError();
+}
+
+} // namespace shw

@@ -1,0 +1,355 @@
+// sweep2d_math.h -- per-cell and per-interface-point arithmetic of the 2D
+// sweep (sec. 3), templated on the real type.
+//
+// Everything here works in the frame of the sweep: "s" is the sweep direction
+// (the interface normal) and "t" the transverse one.  For the x-sweep that is
+// (x, y); the y-sweep runs the same code on the state seen with x and y
+// exchanged (V and Y swapped, the two momentum components swapped), which is
+// the same scheme because the Euler equations are invariant under that map.
+#pragma once
+
+#include "shw_math.h"
+
+namespace shw {
+
+// Index of the pair (a, n), a + n <= 4, in a 15-slot jet: d^{a+n}/ds^a dt^n.
+SHW_HD constexpr int jidx(int a, int n)
+{
+    // rows n = 0..4 hold 5, 4, 3, 2, 1 entries
+    return (n == 0 ? 0 : n == 1 ? 5 : n == 2 ? 9 : n == 3 ? 12 : 14) + a;
+}
+
+// --------------------------------------------------------------------------
+// Stage 1 (sec. 3.2, first step): reconstruction across the sweep, in the
+// transverse direction, of the line averages {W, Y} and of {V, Z} of one cell
+// from the cell and its two transverse neighbours ([0] below, [1] the cell,
+// [2] above).  One weight set (from the {W, Y} data) serves both, as one set
+// of weights serves the function and its derivatives (sec. 2.1.2).  Euler:
+// characteristic fields of the transverse Jacobian at the cell's average.
+// Output: polynomials in eta = (t - t_j)/dt of the cell's line average of W
+// (PW) and of W_s (PV), per conservative component.
+// --------------------------------------------------------------------------
+template <int M, int EQ, class Re>
+SHW_HD void stage1(const Re W[3][M], const Re V[3][M], const Re Y[3][M], const Re Z[3][M],
+                   double dT, bool full, const DevParams &P, Re PW[M][5], Re PV[M][5])
+{
+    if constexpr (EQ == EULER) {
+        if (full && P.charwise) {
+            Re R[M][M], L[M][M], lam[M];
+            euler_eigen<2, 1>(W[1], P.gamma, R, L, lam);
+            Re cw[M][5], cv[M][5];
+#pragma unroll
+            for (int f = 0; f < M; ++f) {
+                Re aw[3], av[3], bw[2], bv[2];
+#pragma unroll
+                for (int l = 0; l < 3; ++l) {
+                    Re sw = 0.0, sv = 0.0;
+#pragma unroll
+                    for (int c = 0; c < M; ++c) {
+                        sw += L[f][c] * W[l][c];
+                        sv += L[f][c] * V[l][c];
+                    }
+                    aw[l] = sw;
+                    av[l] = sv;
+                }
+#pragma unroll
+                for (int l = 0; l < 2; ++l) {
+                    Re sy = 0.0, sz = 0.0;
+#pragma unroll
+                    for (int c = 0; c < M; ++c) {
+                        sy += L[f][c] * Y[2 * l][c];
+                        sz += L[f][c] * Z[2 * l][c];
+                    }
+                    bw[l] = dT * sy;
+                    bv[l] = dT * sz;
+                }
+                Re w[3];
+                big_quartic(aw[0], aw[1], aw[2], bw[0], bw[1], cw[f]);
+                nonlinear_weights(cw[f], aw[0], aw[1], aw[2], P, w);
+                combine(cw[f], aw[0], aw[1], aw[2], w, P);
+                big_quartic(av[0], av[1], av[2], bv[0], bv[1], cv[f]);
+                combine(cv[f], av[0], av[1], av[2], w, P);
+            }
+#pragma unroll
+            for (int c = 0; c < M; ++c)
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    Re sw = 0.0, sv = 0.0;
+#pragma unroll
+                    for (int f = 0; f < M; ++f) {
+                        sw += R[c][f] * cw[f][k];
+                        sv += R[c][f] * cv[f][k];
+                    }
+                    PW[c][k] = sw;
+                    PV[c][k] = sv;
+                }
+            return;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        big_quartic(W[0][c], W[1][c], W[2][c], Re(dT * Y[0][c]), Re(dT * Y[2][c]), PW[c]);
+        big_quartic(V[0][c], V[1][c], V[2][c], Re(dT * Z[0][c]), Re(dT * Z[2][c]), PV[c]);
+        if (full) {
+            Re w[3];
+            nonlinear_weights(PW[c], W[0][c], W[1][c], W[2][c], P, w);
+            combine(PW[c], W[0][c], W[1][c], W[2][c], w, P);
+            combine(PV[c], V[0][c], V[1][c], V[2][c], w, P);
+        }
+    }
+}
+
+// d^n p/deta^n (n = 0..4) of a quartic at eta, times sc[n] (= 1/dt^n).
+template <class Re>
+SHW_HD void derivs_at(const Re c[5], double eta, const double sc[5], Re out[5])
+{
+    const double e2 = eta * eta, e3 = e2 * eta, e4 = e2 * e2;
+    out[0] = (c[0] + eta * c[1] + e2 * c[2] + e3 * c[3] + e4 * c[4]) * sc[0];
+    out[1] = (c[1] + 2.0 * eta * c[2] + 3.0 * e2 * c[3] + 4.0 * e3 * c[4]) * sc[1];
+    out[2] = (2.0 * c[2] + 6.0 * eta * c[3] + 12.0 * e2 * c[4]) * sc[2];
+    out[3] = (6.0 * c[3] + 24.0 * eta * c[4]) * sc[3];
+    out[4] = (24.0 * c[4]) * sc[4];
+}
+
+// d^n p/deta^n of a quartic at eta, times scale.
+template <class Re>
+SHW_HD Re deriv_at(const Re c[5], double eta, int n, double scale)
+{
+    const double e2 = eta * eta, e3 = e2 * eta, e4 = e2 * e2;
+    switch (n) {
+    case 0: return (c[0] + eta * c[1] + e2 * c[2] + e3 * c[3] + e4 * c[4]) * scale;
+    case 1: return (c[1] + 2.0 * eta * c[2] + 3.0 * e2 * c[3] + 4.0 * e3 * c[4]) * scale;
+    case 2: return (2.0 * c[2] + 6.0 * eta * c[3] + 12.0 * e2 * c[4]) * scale;
+    case 3: return (6.0 * c[3] + 24.0 * eta * c[4]) * scale;
+    default: return (24.0 * c[4]) * scale;
+    }
+}
+
+// --------------------------------------------------------------------------
+// Stage 2 (sec. 3.2, second step), one transverse order n at one edge node:
+// reconstruction along the sweep direction from the node values a[l] =
+// d^n/dt^n of the line averages of W of cells l = -1, 0, +1 and b[l] = the
+// same for W_s of cells -1, +1 (scaled by ds inside).  Weights come from the
+// order-0 data (w is filled when n == 0 and reused for n >= 1).  Euler:
+// characteristic fields of the sweep Jacobian at the cell's average (L, R).
+// Writes d^{a+n}W/ds^a dt^n at s = -1/2 (lo[a]) and s = +1/2 (hi[a]), a <= 4 - n.
+// --------------------------------------------------------------------------
+template <int M, int EQ, class Re>
+SHW_HD void stage2_order(int n, const Re am[M], const Re a0[M], const Re ap[M], const Re bm[M],
+                         const Re bp[M], const Re L[M][M], const Re R[M][M], double dS,
+                         const double scs[5], bool full, const DevParams &P, Re w[M][3],
+                         Re lo[5][M], Re hi[5][M])
+{
+    const bool proj = EQ == EULER && full && P.charwise;
+    Re clo[M][5], chi[M][5];
+#pragma unroll
+    for (int f = 0; f < M; ++f) {
+        Re xm, x0, xp, ym, yp;
+        if (proj) {
+            xm = 0.0; x0 = 0.0; xp = 0.0; ym = 0.0; yp = 0.0;
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                xm += L[f][c] * am[c];
+                x0 += L[f][c] * a0[c];
+                xp += L[f][c] * ap[c];
+                ym += L[f][c] * bm[c];
+                yp += L[f][c] * bp[c];
+            }
+        } else {
+            xm = am[f]; x0 = a0[f]; xp = ap[f]; ym = bm[f]; yp = bp[f];
+        }
+        Re q[5];
+        big_quartic(xm, x0, xp, Re(dS * ym), Re(dS * yp), q);
+        if (full) {
+            if (n == 0) nonlinear_weights(q, xm, x0, xp, P, w[f]);
+            combine(q, xm, x0, xp, w[f], P);
+        }
+        edge_derivs(q, clo[f], chi[f]);
+    }
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+        if (a + n > 4) continue;
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            Re l = 0.0, h = 0.0;
+            if (proj) {
+#pragma unroll
+                for (int f = 0; f < M; ++f) {
+                    l += R[c][f] * clo[f][a];
+                    h += R[c][f] * chi[f][a];
+                }
+            } else {
+                l = clo[c][a];
+                h = chi[c][a];
+            }
+            lo[a][c] = l * scs[a];
+            hi[a][c] = h * scs[a];
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// Lax-Wendroff procedure in two space dimensions (sec. 3.1), Euler: the
+// conservative spatial series of the interface state (seeds s[c][a][b],
+// coefficient of s^a t^b, a+b <= 4) is carried to its time layers.  The
+// recursion runs on the primitive variables rho, u, v, p, whose PDE
+// (rho_t = -(u rho_s + rho u_s + v rho_t' + rho v_t'),
+//  u_t = -(u u_s + v u_t' + p_s/rho), v_t likewise, p_t = -(u p_s + v p_t' +
+//  g p (u_s + v_t'))) keeps fewer series alive; the resulting conservative
+// Taylor coefficients are the same numbers (the truncated series of one
+// analytic solution), so only the rounding differs from a conservative-form
+// recursion.  Output: the conservative time coefficients wt[c][k] at the
+// interface point, k = 0..4, i.e. W(tau) = sum_k wt[k] tau^k.
+//   spatial layer: rho = s0; u, v by series division of the momenta by rho;
+//     p = (g-1)(E - (m_s u + m_t v)/2); r = 1/rho by series reciprocal;
+//   level k -> k+1, each coefficient (a,b,k+1) from the Cauchy products of
+//     the level <= k coefficients, divided by -(k+1);
+//   back to conservative: m = rho u, E = p/(g-1) + (m_s u + m_t v)/2 along
+//     the time line (a = b = 0).
+// --------------------------------------------------------------------------
+// The recursion itself is written out as straight-line code by gen_ck2d.py
+// (one named scalar per series coefficient, so it stays in registers).
+} // namespace shw
+#include "ck2d_gen.h"
+namespace shw {
+
+// Linear advection W_t + a W_s + b W_t' = 0 (the same recursion, linear).
+template <class R>
+SHW_HD void ck2d_adv(const R s[5][5], double as, double at, R wt[5])
+{
+    R w[5][5][5];
+#pragma unroll
+    for (int a = 0; a <= 4; ++a)
+#pragma unroll
+        for (int b = 0; a + b <= 4; ++b) w[a][b][0] = s[a][b];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int a = 0; a + k <= 3; ++a)
+#pragma unroll
+            for (int b = 0; a + b + k <= 3; ++b)
+                w[a][b][k + 1] = (-as * (double)(a + 1) / (double)(k + 1)) * w[a + 1][b][k]
+                               + (-at * (double)(b + 1) / (double)(k + 1)) * w[a][b + 1][k];
+#pragma unroll
+    for (int k = 0; k <= 4; ++k) wt[k] = w[0][0][k];
+}
+
+// --------------------------------------------------------------------------
+// GRP at one interface point with normal s (eqs. (taylor2d), (leadingterm2d),
+// (lineq2d)).  grp2d_leading: the leading term from the two order-0 states
+// (HLLC for Euler, upwind for advection) and the eigen-decomposition of the
+// sweep Jacobian there.  grp2d_seed: one derivative d^{a+n}/ds^a dt^n
+// (1 <= a+n <= 4) by upwinding each characteristic field between the cell
+// below (JL, its s = +1/2 side) and above (JR); returns the series
+// coefficient (derivative / (a! n!)).
+// --------------------------------------------------------------------------
+template <int M, int EQ, class Re>
+struct Leading2D {
+    Re Ws[M], R[M][M], L[M][M], lam[M], scale;
+};
+
+template <int M, int EQ, class Re>
+SHW_HD void grp2d_leading(const Re JL[M], const Re JR[M], const DevParams &P, double as,
+                          Leading2D<M, EQ, Re> &G)
+{
+    if constexpr (EQ == EULER) {
+        hllc_state<2>(JL, JR, P.gamma, G.Ws);
+        euler_eigen<2, 0>(G.Ws, P.gamma, G.R, G.L, G.lam);
+        G.scale = 0.0;
+#pragma unroll
+        for (int f = 0; f < M; ++f) G.scale = fmax(G.scale, fabs(G.lam[f]));
+    } else {
+        G.lam[0] = as;
+        G.scale = fabs(as);
+        G.R[0][0] = 1.0;
+        G.L[0][0] = 1.0;
+        G.Ws[0] = upwind(G.lam[0], G.scale, JL[0], JR[0]);
+    }
+}
+
+template <int M, int EQ, class Re>
+SHW_HD void grp2d_seed(const Re JL[M], const Re JR[M], const Leading2D<M, EQ, Re> &G,
+                       double factor, Re out[M])
+{
+    if constexpr (EQ == EULER) {
+        Re ch[M];
+#pragma unroll
+        for (int f = 0; f < M; ++f) {
+            Re l = 0.0, r = 0.0;
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                l += G.L[f][c] * JL[c];
+                r += G.L[f][c] * JR[c];
+            }
+            ch[f] = upwind(G.lam[f], G.scale, l, r);
+        }
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            Re d = 0.0;
+#pragma unroll
+            for (int f = 0; f < M; ++f) d += G.R[c][f] * ch[f];
+            out[c] = d * factor;
+        }
+    } else {
+        out[0] = upwind(G.lam[0], G.scale, JL[0], JR[0]) * factor;
+    }
+}
+
+// The whole GRP from full jets (JL[jidx(a,n)][c]): leading term, all
+// derivatives, Lax-Wendroff; output time coefficients wt[c][k].
+template <int M, int EQ, class Re>
+SHW_HD void grp2d(const Re JL[15][M], const Re JR[15][M], const DevParams &P, double as,
+                  double at, Re wt[M][5])
+{
+    const double inv_fact[5] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
+    Leading2D<M, EQ, Re> G;
+    grp2d_leading<M, EQ>(JL[0], JR[0], P, as, G);
+    Re s[M][5][5];
+#pragma unroll
+    for (int c = 0; c < M; ++c) s[c][0][0] = G.Ws[c];
+#pragma unroll
+    for (int n = 0; n <= 4; ++n)
+#pragma unroll
+        for (int a = 0; a + n <= 4; ++a) {
+            if (a + n == 0) continue;
+            Re o[M];
+            grp2d_seed<M, EQ>(JL[jidx(a, n)], JR[jidx(a, n)], G, inv_fact[a] * inv_fact[n], o);
+#pragma unroll
+            for (int c = 0; c < M; ++c) s[c][a][n] = o[c];
+        }
+    if constexpr (EQ == EULER) ck2d_euler(s, P.gamma, wt);
+    else ck2d_adv(s[0], as, at, wt[0]);
+}
+
+// Flux of eq. (fx2d) at one edge node: 4-point Gauss-Lobatto in time of the
+// s-flux of W(tau); also returns W(t + dt).
+template <int M, int EQ, class Re>
+SHW_HD void node_flux(const Re wt[M][5], double dt, const DevParams &P, double as, Re F[M],
+                      Re We[M])
+{
+    const double taus[4] = {0.0, (0.5 - LOB_H) * dt, (0.5 + LOB_H) * dt, dt};
+    const double wts[4] = {LOB_W0, LOB_W1, LOB_W1, LOB_W0};
+#pragma unroll
+    for (int c = 0; c < M; ++c) F[c] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double tau = taus[q];
+        Re Wt[M], Fq[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+            Wt[c] = wt[c][0] + tau * (wt[c][1] + tau * (wt[c][2] + tau * (wt[c][3] + tau * wt[c][4])));
+        if constexpr (EQ == EULER) {
+            phys_flux_x<EULER, 2>(Wt, P, Fq);
+        } else {
+            Fq[0] = as * Wt[0];
+        }
+#pragma unroll
+        for (int c = 0; c < M; ++c) F[c] += wts[q] * Fq[c];
+        if (q == 3) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) We[c] = Wt[c];
+        }
+    }
+}
+
+} // namespace shw
