@@ -52,7 +52,11 @@ typedef enum {
 
 enum { SHW_ADVECTION = 0, SHW_BURGERS = 1, SHW_EULER = 2 };
 enum { SHW_BC_PERIODIC = 0, SHW_BC_TRANSMISSIVE = 1, SHW_BC_REFLECTIVE = 2 };
-enum { SHW_W_NONLINEAR = 0, SHW_W_LINEAR = 1, SHW_W_GATED = 2 };
+enum { SHW_W_NONLINEAR = 0, SHW_W_LINEAR = 1, SHW_W_GATED = 2, SHW_W_LEARNED = 3 };
+
+/* Number of parameters of the learned gate's network (8-32-32-1):
+ * W1[32][8], b1[32], W2[32][32], b2[32], w3[32], b3, in that order. */
+#define SHW_GATE_NPARAMS 1377
 
 /* One uniform mesh (sec. 2: cells I_j of width dx; sec. 3: cells I_ij).
  * dim 1: nx cells on [x0, x1], ny must be 1.  dim 2: nx x ny cells.
@@ -70,9 +74,11 @@ typedef struct {
  * the device-computed step (sec. 5 uses 0.9); eps: regulariser of the
  * nonlinear weights; lin_w: linear weights of the big stencil and the two
  * small ones (sec. 2.3: 0.994, 0.003, 0.003); charwise: Euler only,
- * reconstruct characteristic fields; weights: SHW_W_*; gate_threshold: gated
- * mode, cells whose gate score is >= threshold take the full nonlinear
- * reconstruction. */
+ * reconstruct characteristic fields; weights: SHW_W_* — NONLINEAR is the
+ * paper's SHWENO (sec. 2.3), LINEAR uses the linear weights everywhere, GATED
+ * takes per-cell flags from shw_set_flags, LEARNED (1D Euler) evaluates the
+ * learned gate in every step; gate_threshold (0 < t < 1): a cell whose gate
+ * score sigmoid(logit) is >= t takes the full nonlinear reconstruction. */
 typedef struct {
     int eq;
     int charwise;
@@ -142,6 +148,48 @@ shw_status shw_advance_to(shw_ctx *ctx, const double *T, long long max_steps,
  * host memory.  Overrides any flags computed by the learned gate until the
  * gate is evaluated again. */
 shw_status shw_set_flags(shw_ctx *ctx, int inst, const uint8_t *flags);
+
+/* ---- learned troubled-cell gate (an addition to the paper's method) ------
+ * A small network scores each cell from 8 features of its own averages
+ * (density and energy jumps to both neighbours, their difference, dx V);
+ * cells scored below the threshold use the linear weights, the rest the full
+ * SHWENO reconstruction.  The network runs in BF16 on the matrix cores with
+ * FP32 accumulation; the scheme itself stays FP64. */
+
+/* Load network parameters (host array of SHW_GATE_NPARAMS floats) into the
+ * context for SHW_W_LEARNED.  Synchronising. */
+shw_status shw_gate_load(shw_ctx *ctx, const float *params);
+
+/* Training data from the method itself, 1D Euler batches: for every cell of
+ * the batch (instances back to back) its 8 features (d_features, device,
+ * [cells][8] floats) and its label (d_labels, device, one byte: 1 if the
+ * characteristic nonlinear reconstruction gives the big stencil less than
+ * 0.95 of its linear weight in some field).  Asynchronous. */
+shw_status shw_gate_data(shw_ctx *ctx, float *d_features, uint8_t *d_labels);
+
+/* Bytes of the packed (matrix-instruction layout) form of the network, and
+ * the packing of host parameters into host memory. */
+size_t shw_gate_packed_bytes(void);
+shw_status shw_gate_pack(const float *params, void *packed);
+
+/* Logits of n samples (d_X: device [n][8] floats) with the packed network
+ * d_packed (device copy of shw_gate_pack's output) on the matrix cores.
+ * Asynchronous on hip_stream. */
+shw_status shw_mlp_logits(const float *d_X, int n, const void *d_packed, float *d_logits,
+                          void *hip_stream);
+
+/* Mean weighted binary cross-entropy of sigmoid(logit) over n samples
+ * (labels d_y in {0,1}, positives weighted by pos_weight) and its gradient
+ * with respect to the FP32 parameters d_params (device, SHW_GATE_NPARAMS):
+ * d_grad and *d_loss are overwritten.  FP32 forward and backward on the
+ * vector units.  Asynchronous. */
+shw_status shw_mlp_grad(const float *d_X, const float *d_y, int n, const float *d_params,
+                        float pos_weight, float *d_grad, float *d_loss, void *hip_stream);
+
+/* One Adam step (beta 0.9/0.999, eps 1e-8) on d_params with moments d_m, d_v
+ * (device, zero before step 1); step counts from 1.  Asynchronous. */
+shw_status shw_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v, int step,
+                        float lr, void *hip_stream);
 
 /* Per-instance status (host array of n_inst): SHW_OK, or SHW_ENONPHYS for an
  * instance that met a non-physical state and stopped.  Synchronising. */

@@ -115,10 +115,12 @@ def lib():
         L.orc_advance2d.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_long, _D, _D, ctypes.POINTER(ctypes.c_long)]
-        if hasattr(L, "orc_mlp_forward"):
-            L.orc_mlp_forward.argtypes = [ctypes.c_int, _D, _D, _D]
-            L.orc_mlp_backward.argtypes = [ctypes.c_int, _D, _D, _D, _D, _D]
-            L.orc_mlp_backward.restype = ctypes.c_double
+        L.orc_mlp_forward.argtypes = [ctypes.c_int, _D, _D, _D]
+        L.orc_mlp_backward.argtypes = [ctypes.c_int, _D, _D, _D, ctypes.c_double, _D]
+        L.orc_mlp_backward.restype = ctypes.c_double
+        L.orc_gate_features1d.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _D,
+                                          ctypes.c_int, _D]
+        L.orc_gate_label1d.argtypes = [P, ctypes.c_int, ctypes.c_double, _D, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -216,6 +218,46 @@ def grp_face(cfg: Config, dim: int, JL, JR) -> np.ndarray:
     w = np.zeros((m, 5, 5, 5))
     lib().orc_grp_face(ctypes.byref(cfg.c()), dim, _p(JL), _p(JR), _p(w))
     return w
+
+
+# ---- learned gate ------------------------------------------------------------
+
+N_PARAMS = 32 * 8 + 32 + 32 * 32 + 32 + 32 + 1
+
+
+def gate_features1d(state, dx, bc=BC_PERIODIC):
+    """(n, 8) features of every cell of a 1D Euler state (2, 3, n)."""
+    st = _f64(state)
+    n = st.shape[-1]
+    out = np.zeros((n, 8))
+    f = np.zeros(8)
+    for j in range(n):
+        lib().orc_gate_features1d(n, bc, dx, _p(st), j, _p(f))
+        out[j] = f
+    return out
+
+
+def gate_labels1d(cfg: Config, state, dx):
+    st = _f64(state)
+    n = st.shape[-1]
+    c = cfg.c()
+    return np.array([lib().orc_gate_label1d(ctypes.byref(c), n, dx, _p(st), j)
+                     for j in range(n)], dtype=np.uint8)
+
+
+def mlp_forward(params, X):
+    p, X = _f64(params), _f64(X)
+    z = np.zeros(X.shape[0])
+    lib().orc_mlp_forward(X.shape[0], _p(p), _p(X), _p(z))
+    return z
+
+
+def mlp_backward(params, X, y, pos_weight=1.0):
+    """Mean weighted BCE of sigmoid(logits) and its gradient (FP64)."""
+    p, X, y = _f64(params), _f64(X), _f64(y)
+    g = np.zeros(N_PARAMS)
+    loss = lib().orc_mlp_backward(X.shape[0], _p(p), _p(X), _p(y), pos_weight, _p(g))
+    return loss, g
 
 
 # ---- time stepping ----------------------------------------------------------

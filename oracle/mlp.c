@@ -1,0 +1,183 @@
+/*
+ * mlp.c -- reference of the learned troubled-cell gate: the cell features,
+ * the training labels, and an FP64 multilayer perceptron with its loss
+ * gradient.
+ * TEST INFRASTRUCTURE ONLY (part of the CPU oracle; see shweno_oracle.h).
+ *
+ * The gate is not part of the paper's method; it decides per cell whether the
+ * full nonlinear reconstruction (sec. 2.3) is needed or the linear weights
+ * (the big-stencil quartic alone) suffice.
+ *
+ * Features of a cell (8, single precision in the GPU code): for each of two
+ * quantities q (1D Euler: density and total energy; 2D Euler: density in x
+ * and y, energy in x and y), with dl, dr the jumps of the cell averages to
+ * the left/right neighbour, log2 of (dl^2 + d), (dr^2 + d) and either
+ * ((dr - dl)^2 + d) and ((dx V)^2 + d) (1D) or the same two jumps in the other
+ * direction (2D, then the quantities are density and energy), scaled by
+ * 1/32; d = 1e-12 keeps logs finite.
+ *
+ * Label of a cell: 1 ("troubled") if the characteristic nonlinear
+ * reconstruction of the cell gives the big quartic a weight below (1 - 0.05)
+ * of its linear weight in any field (1D: along x; 2D: along x from (W, V) or
+ * along y from (W, Y)).
+ *
+ * Network: 8 -> 32 (ReLU) -> 32 (ReLU) -> 1 (logit); parameters in one array
+ * W1[32][8], b1[32], W2[32][32], b2[32], w3[32], b3 (1377 values).
+ * Loss: weighted binary cross-entropy on sigmoid(logit), mean over samples.
+ */
+#include <math.h>
+#include <string.h>
+#include "shweno_oracle.h"
+
+void orc_euler_eigen(double gamma, int dim, int dir, const double *W,
+                     double *lam, double *R, double *L);
+
+#define H 32
+#define NF 8
+#define NPAR (H * NF + H + H * H + H + H + 1)
+
+static double logfeat(double x) { return log2(x + 1e-12) / 32.0; }
+
+/* features of cell j of a 1D Euler state (periodic or transmissive ghosts,
+ * as the sweep's boundary conditions give them) */
+void orc_gate_features1d(int n, int bc, double dx, const double *st, int j, double f[NF])
+{
+    const int m = 3;
+    int jm = j - 1, jp = j + 1;
+    if (bc == ORC_BC_PERIODIC) {
+        jm = (jm + n) % n;
+        jp = jp % n;
+    } else {
+        if (jm < 0) jm = 0;
+        if (jp >= n) jp = n - 1;
+    }
+    const int qs[2] = {0, 2};          /* density, energy */
+    for (int k = 0; k < 2; ++k) {
+        int c = qs[k];
+        double a0 = st[c * n + j], am = st[c * n + jm], ap = st[c * n + jp];
+        double dl = a0 - am, dr = ap - a0;
+        double b = dx * st[(m + c) * n + j];
+        f[4 * k + 0] = logfeat(dl * dl);
+        f[4 * k + 1] = logfeat(dr * dr);
+        f[4 * k + 2] = logfeat((dr - dl) * (dr - dl));
+        f[4 * k + 3] = logfeat(b * b);
+    }
+}
+
+/* 1 if any characteristic field's big-stencil weight falls below 0.95 of
+ * its linear weight (data: averages and dx-scaled derivative averages of
+ * cells -1, 0, +1 along one direction; dim/dir select the eigenvectors) */
+static int troubled_line(const orc_cfg *cfg, int dim, int dir, const double W[3][4],
+                         const double B[2][4])
+{
+    int m = orc_ncomp(cfg->eq, dim);
+    double lam[4], R[16], L[16];
+    orc_euler_eigen(cfg->gamma, dim, dir, W[1], lam, R, L);
+    for (int s = 0; s < m; ++s) {
+        double a[3], b[2], w[3];
+        for (int l = 0; l < 3; ++l) {
+            a[l] = 0.0;
+            for (int c = 0; c < m; ++c) a[l] += L[s * m + c] * W[l][c];
+        }
+        for (int l = 0; l < 2; ++l) {
+            b[l] = 0.0;
+            for (int c = 0; c < m; ++c) b[l] += L[s * m + c] * B[l][c];
+        }
+        orc_weights(cfg, a, b, w);
+        if (w[0] < 0.95 * cfg->lin_w[0]) return 1;
+    }
+    return 0;
+}
+
+int orc_gate_label1d(const orc_cfg *cfg, int n, double dx, const double *st, int j)
+{
+    const int m = 3;
+    double W[3][4], B[2][4];
+    for (int l = 0; l < 3; ++l) {
+        int jj = j - 1 + l;
+        int zero_v = 0;
+        if (jj < 0 || jj >= n) {
+            if (cfg->bc[0] == ORC_BC_PERIODIC) jj = (jj + n) % n;
+            else { jj = jj < 0 ? 0 : n - 1; zero_v = 1; }
+        }
+        for (int c = 0; c < m; ++c) W[l][c] = st[c * n + jj];
+        if (l != 1)
+            for (int c = 0; c < m; ++c)
+                B[l / 2][c] = zero_v ? 0.0 : dx * st[(m + c) * n + jj];
+    }
+    return troubled_line(cfg, 1, 0, W, B);
+}
+
+/* forward pass; h1, h2 (32 each) may be NULL */
+double orc_mlp_logit(const double *p, const double x[NF], double *h1, double *h2)
+{
+    const double *W1 = p, *b1 = W1 + H * NF, *W2 = b1 + H, *b2 = W2 + H * H;
+    const double *w3 = b2 + H, *b3 = w3 + H;
+    double a1[H], a2[H];
+    for (int i = 0; i < H; ++i) {
+        double s = b1[i];
+        for (int k = 0; k < NF; ++k) s += W1[i * NF + k] * x[k];
+        a1[i] = s > 0.0 ? s : 0.0;
+    }
+    for (int i = 0; i < H; ++i) {
+        double s = b2[i];
+        for (int k = 0; k < H; ++k) s += W2[i * H + k] * a1[k];
+        a2[i] = s > 0.0 ? s : 0.0;
+    }
+    double z = b3[0];
+    for (int k = 0; k < H; ++k) z += w3[k] * a2[k];
+    if (h1) memcpy(h1, a1, sizeof a1);
+    if (h2) memcpy(h2, a2, sizeof a2);
+    return z;
+}
+
+/* logits of n samples X[n][8] */
+void orc_mlp_forward(int n, const double *p, const double *X, double *z)
+{
+    for (int s = 0; s < n; ++s) z[s] = orc_mlp_logit(p, X + s * NF, NULL, NULL);
+}
+
+/* mean weighted BCE over n samples and its gradient (grad: NPAR values);
+ * y: labels 0/1 as doubles; pos_w: weight of positive samples */
+double orc_mlp_backward(int n, const double *p, const double *X, const double *y,
+                        double pos_w, double *grad)
+{
+    const double *W1 = p, *b1 = W1 + H * NF, *W2 = b1 + H, *b2 = W2 + H * H;
+    const double *w3 = b2 + H;
+    (void)b1; (void)b2;
+    memset(grad, 0, NPAR * sizeof(double));
+    double *gW1 = grad, *gb1 = gW1 + H * NF, *gW2 = gb1 + H, *gb2 = gW2 + H * H;
+    double *gw3 = gb2 + H, *gb3 = gw3 + H;
+    double loss = 0.0;
+    for (int s = 0; s < n; ++s) {
+        const double *x = X + s * NF;
+        double h1[H], h2[H];
+        double z = orc_mlp_logit(p, x, h1, h2);
+        double sig = 1.0 / (1.0 + exp(-z));
+        double w = y[s] > 0.5 ? pos_w : 1.0;
+        /* loss = -w [y log s + (1-y) log(1-s)], stable form */
+        double lz = z > 0 ? z + log1p(exp(-z)) : log1p(exp(z));   /* log(1+e^z) */
+        loss += w * (lz - y[s] * z);
+        double dz = w * (sig - y[s]) / n;
+        gb3[0] += dz;
+        double d2[H], d1[H];
+        for (int k = 0; k < H; ++k) {
+            gw3[k] += dz * h2[k];
+            d2[k] = h2[k] > 0.0 ? dz * w3[k] : 0.0;
+        }
+        for (int i = 0; i < H; ++i) {
+            gb2[i] += d2[i];
+            for (int k = 0; k < H; ++k) gW2[i * H + k] += d2[i] * h1[k];
+        }
+        for (int k = 0; k < H; ++k) {
+            double s1 = 0.0;
+            for (int i = 0; i < H; ++i) s1 += W2[i * H + k] * d2[i];
+            d1[k] = h1[k] > 0.0 ? s1 : 0.0;
+        }
+        for (int i = 0; i < H; ++i) {
+            gb1[i] += d1[i];
+            for (int k = 0; k < NF; ++k) gW1[i * NF + k] += d1[i] * x[k];
+        }
+    }
+    return loss / n;
+}

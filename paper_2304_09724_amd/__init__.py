@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libshweno.so")
 
 ADVECTION, BURGERS, EULER = 0, 1, 2
 BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE = 0, 1, 2
-W_NONLINEAR, W_LINEAR, W_GATED = 0, 1, 2
+W_NONLINEAR, W_LINEAR, W_GATED, W_LEARNED = 0, 1, 2, 3
+GATE_NPARAMS = 1377
 STATUS = {0: "SHW_OK", -1: "SHW_EINVAL", -2: "SHW_ENOMEM", -3: "SHW_EDEVICE",
           -4: "SHW_ENONPHYS", -5: "SHW_ESTATE"}
 
@@ -88,6 +89,14 @@ def lib():
         L.shw_step.argtypes = [vp, _D]
         L.shw_advance_to.argtypes = [vp, _D, ctypes.c_longlong, _LL]
         L.shw_instance_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+        FP = ctypes.POINTER(ctypes.c_float)
+        L.shw_gate_load.argtypes = [vp, FP]
+        L.shw_gate_data.argtypes = [vp, vp, vp]
+        L.shw_gate_packed_bytes.restype = ctypes.c_size_t
+        L.shw_gate_pack.argtypes = [FP, vp]
+        L.shw_mlp_logits.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+        L.shw_mlp_grad.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_float, vp, vp, vp]
+        L.shw_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, vp]
         L.shw_set_flags.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8)]
         L.shw_status_detail.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_char_p,
                                         ctypes.c_size_t]
@@ -97,6 +106,55 @@ def lib():
 
 def _dptr(a: np.ndarray):
     return a.ctypes.data_as(_D)
+
+
+def _check_free(code, what):
+    if code != 0:
+        raise ShwError(code, what)
+
+
+def _vp(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def gate_pack(params) -> np.ndarray:
+    """Packed (matrix-instruction layout) network from FP32 parameters."""
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+    assert p.size == GATE_NPARAMS
+    out = np.zeros(lib().shw_gate_packed_bytes(), dtype=np.uint8)
+    _check_free(lib().shw_gate_pack(p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                    out.ctypes.data_as(ctypes.c_void_p)), "gate_pack")
+    return out
+
+
+def mlp_logits(X, packed):
+    """Logits of the samples X (cuda float32 [n, 8]) with a packed network
+    (cuda uint8 tensor), on the matrix cores."""
+    import torch
+    n = X.shape[0]
+    out = torch.empty(n, dtype=torch.float32, device=X.device)
+    _check_free(lib().shw_mlp_logits(_vp(X), n, _vp(packed), _vp(out), _stream_ptr()), "mlp_logits")
+    return out
+
+
+def mlp_grad(X, y, params, pos_weight=1.0):
+    """(loss, grad) of the weighted BCE on cuda tensors (FP32)."""
+    import torch
+    g = torch.empty(GATE_NPARAMS, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    _check_free(lib().shw_mlp_grad(_vp(X), _vp(y), X.shape[0], _vp(params), pos_weight,
+                                   _vp(g), _vp(loss), _stream_ptr()), "mlp_grad")
+    return loss, g
+
+
+def mlp_adam(params, grad, m, v, step, lr):
+    _check_free(lib().shw_mlp_adam(_vp(params), _vp(grad), _vp(m), _vp(v), step, lr,
+                                   _stream_ptr()), "mlp_adam")
 
 
 class Solver:
@@ -200,6 +258,21 @@ class Solver:
         if not (code == -4 and not raise_nonphysical):
             self._check(code)
         return steps
+
+    def gate_load(self, params):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        assert p.size == GATE_NPARAMS
+        self._check(lib().shw_gate_load(self.ctx, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def gate_data(self):
+        """(features [cells, 8] float32, labels [cells] uint8) cuda tensors for
+        every cell of the (1D Euler) batch in its current state."""
+        torch = self.torch
+        cells = sum(m.nx * m.ny for m in self.meshes)
+        f = torch.empty((cells, 8), dtype=torch.float32, device=self.device)
+        lab = torch.empty(cells, dtype=torch.uint8, device=self.device)
+        self._check(lib().shw_gate_data(self.ctx, _vp(f), _vp(lab)))
+        return f, lab
 
     def set_flags(self, i, flags):
         f = np.ascontiguousarray(np.asarray(flags, dtype=np.uint8).reshape(-1))

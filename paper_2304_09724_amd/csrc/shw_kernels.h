@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "shw_math.h"
+#include "gate_math.h"
 
 namespace shw {
 
@@ -49,6 +50,8 @@ struct Loop1D {
     long long max_steps;       // per instance step limit for this launch
     InstState *ist;
     const uint8_t *flags;      // per cell gate flags (GATED mode)
+    const GateLane *gate;      // packed network (LEARNED mode)
+    float gate_logit_min;      // cells with logit >= this take the full reconstruction
 };
 
 // Launch parameters of one 2D step over a batch (all pointers device-side).
@@ -77,6 +80,15 @@ hipError_t launch_speed2d(int eq, const Step2D &S, const DevParams &P, int use_p
 hipError_t launch_step2d(int eq, const Step2D &S, const DevParams &P, int fixed,
                          const int total_tiles[2], hipStream_t stream);
 hipError_t launch_settle2d(const Step2D &S, int m, hipStream_t stream);
+
+hipError_t launch_gate_data1d(const Inst1D *inst, int n_inst, int max_n, const double *state,
+                              const DevParams &P, float *feat, uint8_t *label, hipStream_t stream);
+hipError_t launch_mlp_logits(const float *X, int n, const GateLane *G, float *logits,
+                             hipStream_t stream);
+hipError_t launch_mlp_grad(const float *X, const float *y, int n, const float *p, float pos_w,
+                           float *grad, float *loss, hipStream_t stream);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int t, float lr,
+                       hipStream_t stream);
 
 hipError_t launch_loop1d(int eq, const Loop1D &L, const DevParams &P, int grid,
                          hipStream_t stream);

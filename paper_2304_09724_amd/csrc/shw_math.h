@@ -17,7 +17,7 @@ namespace shw {
 
 enum { ADV = 0, BURG = 1, EULER = 2 };
 enum { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
-enum { W_NONLINEAR = 0, W_LINEAR = 1, W_GATED = 2 };
+enum { W_NONLINEAR = 0, W_LINEAR = 1, W_GATED = 2, W_LEARNED = 3 };
 
 // Scheme parameters as the kernels see them.
 struct DevParams {

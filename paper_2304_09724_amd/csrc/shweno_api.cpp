@@ -27,7 +27,9 @@ bool valid_params(const shw_params *p)
 {
     if (!p) return false;
     if (p->eq < SHW_ADVECTION || p->eq > SHW_EULER) return false;
-    if (p->weights < SHW_W_NONLINEAR || p->weights > SHW_W_GATED) return false;
+    if (p->weights < SHW_W_NONLINEAR || p->weights > SHW_W_LEARNED) return false;
+    if (p->weights == SHW_W_LEARNED && !(p->gate_threshold > 0.0 && p->gate_threshold < 1.0))
+        return false;
     if (p->eq == SHW_EULER && !(p->gamma > 1.0)) return false;
     if (!(p->cfl > 0.0) || !(p->eps > 0.0)) return false;
     for (int k = 0; k < 3; ++k)
@@ -60,7 +62,7 @@ size_t state_doubles(const shw_mesh *m, int eq)
 struct Layout {
     size_t alt = 0, inst = 0, order = 0, queue = 0, ist = 0, t_end = 0, dt = 0,
            flags = 0, tiles0 = 0, tiles1 = 0, parity = 0, last = 0, dt_fixed = 0,
-           steps_left = 0, smax = 0, bad = 0, active = 0, total = 0;
+           steps_left = 0, smax = 0, bad = 0, active = 0, gate = 0, total = 0;
 };
 
 Layout make_layout(const shw_mesh *meshes, int n_inst, const shw_params *p)
@@ -90,6 +92,7 @@ Layout make_layout(const shw_mesh *meshes, int n_inst, const shw_params *p)
     L.smax = take((size_t)n_inst * sizeof(double));
     L.bad = take((size_t)n_inst * sizeof(int));
     L.active = take(256);
+    L.gate = take(64 * sizeof(GateLane));
     L.total = off;
     return L;
 }
@@ -108,6 +111,7 @@ struct shw_ctx {
     hipStream_t stream = nullptr;
     int grid1d = 1;
     int tiles2d[2] = {0, 0};
+    bool gate_loaded = false;
     int bad_instance = -1;
     std::string msg;
 
@@ -152,6 +156,8 @@ shw_status shw_create(const shw_mesh *meshes, int n_inst, const shw_params *para
     for (int i = 0; i < n_inst; ++i)
         if (!valid_mesh(&meshes[i]) || meshes[i].dim != meshes[0].dim) return SHW_EINVAL;
     if (params->eq == SHW_BURGERS && meshes[0].dim != 1) return SHW_EINVAL;
+    if (params->weights == SHW_W_LEARNED && (params->eq != SHW_EULER || meshes[0].dim != 1))
+        return SHW_EINVAL;
     shw_ctx *c = new (std::nothrow) shw_ctx;
     if (!c) return SHW_ENOMEM;
     c->n_inst = n_inst;
@@ -408,6 +414,9 @@ static Loop1D loop_args(shw_ctx *c)
     L.alt = c->alt();
     L.ist = c->ist();
     L.flags = c->at<uint8_t>(c->lay.flags);
+    L.gate = c->at<GateLane>(c->lay.gate);
+    const double th = c->params.gate_threshold;
+    L.gate_logit_min = (th > 0.0 && th < 1.0) ? (float)std::log(th / (1.0 - th)) : 0.0f;
     return L;
 }
 
@@ -416,6 +425,8 @@ shw_status shw_step(shw_ctx *c, const double *dt)
     if (!c || !dt) return SHW_EINVAL;
     for (int i = 0; i < c->n_inst; ++i)
         if (!std::isfinite(dt[i])) return SHW_EINVAL;
+    if (c->params.weights == SHW_W_LEARNED && !c->gate_loaded)
+        return c->fail(SHW_ESTATE, "learned gate not loaded");
     if (c->dim == 2) {
         Step2D S = step2d_args(c);
         shw_status s = c->hip(hipMemcpyAsync(const_cast<double *>(S.dt_fixed), dt,
@@ -472,6 +483,8 @@ shw_status shw_advance_to(shw_ctx *c, const double *T, long long max_steps, long
     if (!c || !T || max_steps < 0) return SHW_EINVAL;
     for (int i = 0; i < c->n_inst; ++i)
         if (!std::isfinite(T[i])) return SHW_EINVAL;
+    if (c->params.weights == SHW_W_LEARNED && !c->gate_loaded)
+        return c->fail(SHW_ESTATE, "learned gate not loaded");
     std::vector<InstState> before;
     shw_status s = read_ist(c, before);
     if (s != SHW_OK) return s;
@@ -513,6 +526,90 @@ shw_status shw_set_flags(shw_ctx *c, int inst, const uint8_t *flags)
                                          hipMemcpyHostToDevice, c->stream), "set_flags");
     if (s != SHW_OK) return s;
     return c->hip(hipStreamSynchronize(c->stream), "set_flags sync");
+}
+
+static unsigned short host_bf16(float f)
+{
+    unsigned u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+size_t shw_gate_packed_bytes(void) { return 64 * sizeof(GateLane); }
+
+shw_status shw_gate_pack(const float *p, void *packed)
+{
+    if (!p || !packed) return SHW_EINVAL;
+    const float *W1 = p, *b1 = W1 + GATE_H * 8, *W2 = b1 + GATE_H, *b2 = W2 + GATE_H * GATE_H;
+    const float *w3 = b2 + GATE_H, *b3 = w3 + GATE_H;
+    GateLane *out = static_cast<GateLane *>(packed);
+    std::memset(out, 0, 64 * sizeof(GateLane));
+    for (int lane = 0; lane < 64; ++lane) {
+        GateLane &L = out[lane];
+        const int r = lane % 32, h = lane / 32;
+        for (int e = 0; e < 4; ++e) {
+            L.w1[e] = (short)host_bf16(W1[r * 8 + 4 * h + e]);
+            for (int q = 0; q < 4; ++q) L.w2[q][e] = (short)host_bf16(W2[r * GATE_H + 8 * q + 4 * h + e]);
+        }
+        for (int v = 0; v < 16; ++v) {
+            const int row = mfma_row(lane, v);
+            L.b1[v] = b1[row];
+            L.b2[v] = b2[row];
+            L.w3[v] = w3[row];
+        }
+        L.b3 = b3[0];
+    }
+    return SHW_OK;
+}
+
+shw_status shw_gate_load(shw_ctx *c, const float *params)
+{
+    if (!c || !params) return SHW_EINVAL;
+    std::vector<GateLane> packed(64);
+    shw_gate_pack(params, packed.data());
+    shw_status s = c->hip(hipMemcpyAsync(c->ws + c->lay.gate, packed.data(), 64 * sizeof(GateLane),
+                                         hipMemcpyHostToDevice, c->stream), "gate load");
+    if (s != SHW_OK) return s;
+    s = c->hip(hipStreamSynchronize(c->stream), "gate load sync");
+    if (s == SHW_OK) c->gate_loaded = true;
+    return s;
+}
+
+shw_status shw_gate_data(shw_ctx *c, float *d_features, uint8_t *d_labels)
+{
+    if (!c || !d_features || !d_labels) return SHW_EINVAL;
+    if (c->dim != 1 || c->params.eq != SHW_EULER)
+        return c->fail(SHW_EINVAL, "gate data: 1D Euler only");
+    int max_n = 0;
+    for (const auto &m : c->meshes) max_n = std::max(max_n, m.nx);
+    return c->hip(launch_gate_data1d(c->at<Inst1D>(c->lay.inst), c->n_inst, max_n, c->state, c->dp,
+                                     d_features, d_labels, c->stream), "gate data");
+}
+
+shw_status shw_mlp_logits(const float *d_X, int n, const void *d_packed, float *d_logits,
+                          void *stream)
+{
+    if (!d_X || n < 1 || !d_packed || !d_logits) return SHW_EINVAL;
+    return launch_mlp_logits(d_X, n, static_cast<const GateLane *>(d_packed), d_logits,
+                             static_cast<hipStream_t>(stream)) == hipSuccess ? SHW_OK : SHW_EDEVICE;
+}
+
+shw_status shw_mlp_grad(const float *d_X, const float *d_y, int n, const float *d_params,
+                        float pos_weight, float *d_grad, float *d_loss, void *stream)
+{
+    if (!d_X || !d_y || n < 1 || !d_params || !d_grad || !d_loss || !(pos_weight > 0.0f))
+        return SHW_EINVAL;
+    return launch_mlp_grad(d_X, d_y, n, d_params, pos_weight, d_grad, d_loss,
+                           static_cast<hipStream_t>(stream)) == hipSuccess ? SHW_OK : SHW_EDEVICE;
+}
+
+shw_status shw_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v, int step,
+                        float lr, void *stream)
+{
+    if (!d_params || !d_grad || !d_m || !d_v || step < 1 || !(lr > 0.0f)) return SHW_EINVAL;
+    return launch_adam(d_params, d_grad, d_m, d_v, step, lr, static_cast<hipStream_t>(stream)) ==
+                   hipSuccess ? SHW_OK : SHW_EDEVICE;
 }
 
 shw_status shw_status_detail(shw_ctx *c, int *bad_instance, char *msg, size_t msg_len)

@@ -27,40 +27,6 @@ constexpr int WAVE = 64;
 constexpr int BLOCK = 256;
 constexpr int CHUNK = WAVE - 2;
 
-// data of cell j of a 1D instance (ghost cells by the boundary conditions:
-// periodic wrap; transmissive copies the nearest average with a zero
-// derivative average; reflective mirrors, odd quantities change sign)
-template <int EQ, int M>
-__device__ __forceinline__ int load_cell(const double *__restrict__ base, int n, int j,
-                                         int bc_lo, int bc_hi, double W[M], double V[M])
-{
-    int s = j;
-    int kind = -1;   // -1 interior, else the boundary condition in force
-    if (j < 0 || j >= n) {
-        kind = j < 0 ? bc_lo : bc_hi;
-        if (kind == BC_PERIODIC) s = j < 0 ? j + n : j - n;
-        else if (kind == BC_TRANSMISSIVE) s = j < 0 ? 0 : n - 1;
-        else s = j < 0 ? -1 - j : 2 * n - 1 - j;
-    }
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-        W[c] = base[c * n + s];
-        V[c] = base[(M + c) * n + s];
-    }
-    if (kind == BC_TRANSMISSIVE) {
-#pragma unroll
-        for (int c = 0; c < M; ++c) V[c] = 0.0;
-    } else if (kind == BC_REFLECTIVE) {
-#pragma unroll
-        for (int c = 0; c < M; ++c) {
-            const bool odd = EQ == EULER && c == 1;
-            if (odd) W[c] = -W[c]; else V[c] = -V[c];
-        }
-    }
-    return s;
-}
-
-
 template <int EQ>
 __device__ __forceinline__ bool bad_state(const double *W, const DevParams &P)
 {
@@ -88,7 +54,8 @@ template <int EQ>
 __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__restrict__ src,
                                                double *__restrict__ dst, double dt,
                                                const DevParams &P,
-                                               const uint8_t *__restrict__ flags)
+                                               const uint8_t *__restrict__ flags,
+                                               const GateLane *gate, float gate_logit_min)
 {
     constexpr int M = NComp<EQ, 1>::M;
     const int lane = threadIdx.x % WAVE;
@@ -99,23 +66,24 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
     for (int ch = wave; ch < nchunk; ch += BLOCK / WAVE) {
         const int j = ch * CHUNK + lane - 1;       // this lane's cell, -1..n+61
         const bool live = j <= n;
-        double lo[5][M], hi[5][M], W0[M];
-        if (live) {
-            double Wm[M], Vm[M], Wp[M], Vp[M], V0[M];
-            load_cell<EQ, M>(src, n, j - 1, d.bc_lo, d.bc_hi, Wm, Vm);
-            const int s0 = load_cell<EQ, M>(src, n, j, d.bc_lo, d.bc_hi, W0, V0);
-            load_cell<EQ, M>(src, n, j + 1, d.bc_lo, d.bc_hi, Wp, Vp);
-            bool full = P.weights == W_NONLINEAR;
-            if (P.weights == W_GATED) full = flags[d.cell_off + s0] != 0;
-            recon_cell<EQ, M>(Wm, W0, Wp, Vm, Vp, d.dx, full, P, lo, hi);
-        } else {
-#pragma unroll
-            for (int a = 0; a < 5; ++a)
-#pragma unroll
-                for (int c = 0; c < M; ++c) { lo[a][c] = 1.0; hi[a][c] = 1.0; }
-#pragma unroll
-            for (int c = 0; c < M; ++c) W0[c] = 1.0;
+        // lanes past the end read the last ghost cell and discard the result
+        const int jl = live ? j : n;
+        double Wm[M], Vm[M], W0[M], V0[M], Wp[M], Vp[M];
+        load_cell<EQ, M>(src, n, jl - 1, d.bc_lo, d.bc_hi, Wm, Vm);
+        const int s0 = load_cell<EQ, M>(src, n, jl, d.bc_lo, d.bc_hi, W0, V0);
+        load_cell<EQ, M>(src, n, jl + 1, d.bc_lo, d.bc_hi, Wp, Vp);
+        bool full = P.weights == W_NONLINEAR;
+        if (P.weights == W_GATED) full = flags[d.cell_off + s0] != 0;
+        if constexpr (EQ == EULER) {
+            if (P.weights == W_LEARNED) {
+                // the whole wave evaluates the network for its 64 cells
+                float f[8];
+                gate_features1d(Wm, W0, Wp, V0, d.dx, f);
+                full = gate_wave_logit(f, gate[lane]) >= gate_logit_min;
+            }
         }
+        double lo[5][M], hi[5][M];
+        recon_cell<EQ, M>(Wm, W0, Wp, Vm, Vp, d.dx, full, P, lo, hi);
         // right-edge jet of the left neighbour
         double prev[5][M];
 #pragma unroll
@@ -155,7 +123,15 @@ __global__ void __launch_bounds__(BLOCK) loop1d_kernel(Loop1D Lp, DevParams P)
     constexpr int M = NComp<EQ, 1>::M;
     __shared__ int s_item;
     __shared__ double s_red[BLOCK / WAVE];
+    __shared__ GateLane s_gate[EQ == EULER ? WAVE : 1];
     const int tid = threadIdx.x;
+    if (EQ == EULER && P.weights == W_LEARNED) {
+        // the packed network, one slot per lane position, shared by the waves
+        const int words = (int)(sizeof(GateLane) / 4) * WAVE;
+        for (int e = tid; e < words; e += BLOCK)
+            reinterpret_cast<unsigned *>(s_gate)[e] = reinterpret_cast<const unsigned *>(Lp.gate)[e];
+        __syncthreads();
+    }
     for (;;) {
         if (tid == 0) s_item = atomicAdd(Lp.queue, 1);
         __syncthreads();
@@ -199,7 +175,7 @@ __global__ void __launch_bounds__(BLOCK) loop1d_kernel(Loop1D Lp, DevParams P)
                 dt = P.cfl * d.dx / smax;
                 if (dt >= T - st.t) { dt = T - st.t; last = true; }
             }
-            const bool bad = sweep_instance<EQ>(d, A, B, dt, P, Lp.flags);
+            const bool bad = sweep_instance<EQ>(d, A, B, dt, P, Lp.flags, s_gate, Lp.gate_logit_min);
             const int any_bad = __syncthreads_or(bad);
             double *tmp = A; A = B; B = tmp;
             ++k;

@@ -6,6 +6,40 @@
 
 namespace shw {
 
+// data of cell j of a 1D instance (ghost cells by the boundary conditions:
+// periodic wrap; transmissive copies the nearest average with a zero
+// derivative average; reflective mirrors, odd quantities change sign)
+template <int EQ, int M>
+__device__ __forceinline__ int load_cell(const double *__restrict__ base, int n, int j,
+                                         int bc_lo, int bc_hi, double W[M], double V[M])
+{
+    int s = j;
+    int kind = -1;   // -1 interior, else the boundary condition in force
+    if (j < 0 || j >= n) {
+        kind = j < 0 ? bc_lo : bc_hi;
+        if (kind == BC_PERIODIC) s = j < 0 ? j + n : j - n;
+        else if (kind == BC_TRANSMISSIVE) s = j < 0 ? 0 : n - 1;
+        else s = j < 0 ? -1 - j : 2 * n - 1 - j;
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        W[c] = base[c * n + s];
+        V[c] = base[(M + c) * n + s];
+    }
+    if (kind == BC_TRANSMISSIVE) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) V[c] = 0.0;
+    } else if (kind == BC_REFLECTIVE) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            const bool odd = EQ == EULER && c == 1;
+            if (odd) W[c] = -W[c]; else V[c] = -V[c];
+        }
+    }
+    return s;
+}
+
+
 // Step 1: reconstruction of one cell; lo/hi receive d^a W/dx^a at the left
 // and right edge, a = 0..4.
 template <int EQ, int M, class Re>

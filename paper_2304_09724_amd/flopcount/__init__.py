@@ -33,6 +33,10 @@ def euler1d_cell_update(full: bool = True) -> dict:
     return counts()["euler1d_nonlinear_charwise" if full else "euler1d_linear"]
 
 
+def euler2d_cell_update(full: bool = True) -> dict:
+    return counts()["euler2d_nonlinear_charwise" if full else "euler2d_linear"]
+
+
 if __name__ == "__main__":
     for k, v in counts().items():
         print(k, v)

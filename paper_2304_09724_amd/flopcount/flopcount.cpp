@@ -48,6 +48,7 @@ static inline Cnt fmin(Cnt a, Cnt b) { return std::fmin(a.v, b.v); }
 static inline Cnt fmax(Cnt a, Cnt b) { return std::fmax(a.v, b.v); }
 
 #include "../csrc/sweep1d_math.h"
+#include "../csrc/sweep2d_math.h"
 
 using namespace shw;
 
@@ -83,9 +84,85 @@ static void euler1d(bool full, const char *name)
     report(name, g, "cell-update");
 }
 
+// one 2D Euler cell-update: per direction, stage 1 of the cell, and at each
+// of the 4 edge nodes stage 2 (5 transverse orders, incl. the node values of
+// the stage-1 polynomials), the GRP of one interface node and its
+// Gauss-Lobatto flux, then the update; plus the CFL speed of the new average.
+static void euler2d(bool full, const char *name)
+{
+    DevParams P{};
+    P.gamma = 1.4; P.cfl = 0.9; P.eps = 1e-6;
+    P.g1 = 0.994; P.g2 = 0.003; P.g3 = 0.003;
+    P.charwise = 1;
+    P.weights = full ? W_NONLINEAR : W_LINEAR;
+    constexpr int M = 4;
+    Cnt W[3][M], V[3][M], Y[3][M], Z[3][M];
+    for (int l = 0; l < 3; ++l)
+        for (int c = 0; c < M; ++c) {
+            W[l][c] = c == 0 ? 1.0 + 0.1 * l : (c == 3 ? 2.6 + 0.1 * l : 0.1 * (c + l));
+            V[l][c] = 0.01 * (l + c + 1);
+            Y[l][c] = 0.02 * (l - c);
+            Z[l][c] = 0.003 * (l + 2 * c);
+        }
+    const double sc[5] = {1.0, 100.0, 1e4, 1e6, 1e8};
+    g = Tally();
+    for (int dir = 0; dir < 2; ++dir) {
+        Cnt PW[M][5], PV[M][5];
+        stage1<M, EULER>(W, V, Y, Z, 0.01, full, P, PW, PV);
+        for (int gn = 0; gn < 4; ++gn) {
+            const double eta = gn == 0 ? -0.5 : gn == 1 ? -LOB_H : gn == 2 ? LOB_H : 0.5;
+            Cnt Lm[M][M], Rm[M][M], lam[M];
+            euler_eigen<2, 0>(W[1], P.gamma, Rm, Lm, lam);
+            Cnt w[M][3], lo[5][M], hi[5][M];
+            Cnt JL[15][M], JR[15][M];
+            for (int n = 0; n <= 4; ++n) {
+                Cnt a0[M], b0[M];
+                for (int c = 0; c < M; ++c) {
+                    a0[c] = deriv_at(PW[c], eta, n, sc[n]);
+                    b0[c] = deriv_at(PV[c], eta, n, sc[n]);
+                }
+                stage2_order<M, EULER>(n, a0, a0, a0, b0, b0, Lm, Rm, 0.01, sc, full, P, w, lo, hi);
+                for (int a = 0; a + n <= 4; ++a)
+                    for (int c = 0; c < M; ++c) {
+                        JL[jidx(a, n)][c] = hi[a][c];
+                        JR[jidx(a, n)][c] = lo[a][c];
+                    }
+            }
+            Cnt wt[M][5], F[M], We[M];
+            grp2d<M, EULER>(JL, JR, P, 0.0, 0.0, wt);
+            node_flux<M, EULER>(wt, 0.002, P, 0.0, F, We);
+            // flux and edge-node accumulation (kernel: Fh += w_g F; dv, corner terms)
+            for (int c = 0; c < M; ++c) {
+                Cnt acc = LOB_W1 * F[c];
+                Cnt dv = LOB_W1 * (We[c] - We[c]);
+                (void)acc; (void)dv;
+            }
+        }
+        // update: W -= r (Fu - Fh); Z half: 0.5 (a - b - c + d) * inv
+        for (int c = 0; c < M; ++c) {
+            Cnt Wn = W[1][c] - 0.3 * (W[0][c] - W[2][c]);
+            Cnt zc = 0.5 * (W[0][c] - W[1][c] - W[2][c] + W[0][c]) * 100.0;
+            Cnt vn = (W[0][c] + W[1][c]) * 100.0;
+            (void)Wn; (void)zc; (void)vn;
+        }
+    }
+    // CFL speed of the new average
+    {
+        Cnt ir = 1.0 / W[1][0];
+        Cnt u = W[1][1] * ir, v = W[1][2] * ir;
+        Cnt p = (P.gamma - 1.0) * (W[1][3] - 0.5 * W[1][0] * (u * u + v * v));
+        Cnt c = sqrt(P.gamma * p * ir);
+        Cnt sp = (fabs(u) + c) * 100.0 + (fabs(v) + c) * 100.0;
+        (void)sp;
+    }
+    report(name, g, "cell-update");
+}
+
 int main()
 {
     euler1d(true, "euler1d_nonlinear_charwise");
     euler1d(false, "euler1d_linear");
+    euler2d(true, "euler2d_nonlinear_charwise");
+    euler2d(false, "euler2d_linear");
     return 0;
 }
