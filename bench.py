@@ -78,12 +78,82 @@ def cpu_baseline(insts, states, budget_threads=None):
                       f"{wall:.1f} s wall"}
 
 
+def exact_density(d, t, sub=16):
+    """Exact cell averages of the density of a Riemann instance at time t."""
+    import oracle as O
+    e = np.linspace(d.x0, d.x1, d.n + 1)
+    xs = e[:-1, None] + (np.arange(sub) + 0.5) / sub * d.dx
+    out = np.empty(xs.shape)
+    for j in range(d.n):
+        for k in range(sub):
+            out[j, k] = O.exact_riemann(1.4, d.left, d.right, (xs[j, k] - 0.5) / t)[0][0]
+    return out.mean(axis=1)
+
+
+def gated_leg(S, insts, states, meshes, init, args, plain_value, plain):
+    """The same job with the learned gate: network trained on the GPU from
+    plain runs of separate seeded problems (untimed), then K timed steps; L1
+    error against the exact solution compared with the plain run on a sample
+    of instances both complete."""
+    import torch
+    from paper_2304_09724_amd import gate as GT
+    log("gate: training data and training ...")
+    t0 = time.perf_counter()
+    X, y = GT.collect(GT.training_problems(), times=[0.0, 0.02, 0.06, 0.1, 0.14])
+    params, hist = GT.train(X, y)
+    train_s = time.perf_counter() - t0
+    threshold = 0.05
+    g = S.Solver(meshes, S.Params.make(eq=S.EULER, cfl=0.9, weights=S.W_LEARNED,
+                                       gate_threshold=threshold), device="cuda:0")
+    g.gate_load(params)
+    zeros = np.zeros(COUNT)
+    T = np.full(COUNT, T_END)
+    ncell = np.array([d.n for d in insts], dtype=np.int64)
+    for _ in range(args.warmup):
+        g.state.copy_(init)
+        g.set_times(zeros)
+        g.advance_to(T, raise_nonphysical=False)
+    torch.cuda.synchronize()
+    cus = []
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        g.state.copy_(init)
+        g.set_times(zeros)
+        steps = g.advance_to(T, raise_nonphysical=False)
+        cus.append(int((ncell * steps).sum()))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    value = float(np.mean(cus)) * args.steps / wall
+    okg, okp = g.instance_status() == 0, plain.instance_status() == 0
+    sample = [i for i in range(COUNT) if okg[i] and okp[i]][:24]
+    l1p = l1g = tvp = tvg = 0.0
+    for i in sample:
+        ex = exact_density(insts[i], T_END)
+        rp, rg = plain.get_state(i)[0, 0], g.get_state(i)[0, 0]
+        l1p += np.abs(rp - ex).mean()
+        l1g += np.abs(rg - ex).mean()
+        tvp += np.abs(np.diff(rp)).sum()
+        tvg += np.abs(np.diff(rg)).sum()
+    # fraction of cells the gate passes as smooth, over the training data
+    z = S.mlp_logits(X, torch.from_numpy(S.gate_pack(params)).to(X.device)).cpu().numpy()
+    smooth = float((z < np.log(threshold / (1 - threshold))).mean())
+    return {"value": value, "unit": "cell-updates/s", "speedup_vs_plain": value / plain_value,
+            "ms_per_step": wall / args.steps * 1e3, "gate_threshold": threshold,
+            "l1_ratio_gated_over_plain": l1g / l1p, "l1_sample_instances": len(sample),
+            "total_variation_ratio_gated_over_plain": tvg / tvp,
+            "nonphysical_instances": int((~okg).sum()),
+            "smooth_fraction_training_cells": smooth,
+            "training": {"samples": int(X.shape[0]), "adam_steps": 800,
+                         "loss_first_last": [hist[0], hist[-1]], "seconds": round(train_s, 2)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gate", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the batch would be "
@@ -161,6 +231,8 @@ def main():
                                           "updates actually performed are counted",
                       "parallelism": "single GPU, one persistent launch"},
            "roofline": roofline}
+    if not args.no_gate:
+        out["gated"] = gated_leg(S, insts, states, meshes, init, args, value, solver)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(insts, states)

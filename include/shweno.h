@@ -56,7 +56,8 @@ enum { SHW_W_NONLINEAR = 0, SHW_W_LINEAR = 1, SHW_W_GATED = 2, SHW_W_LEARNED = 3
 
 /* Number of parameters of the learned gate's network (8-32-32-1):
  * W1[32][8], b1[32], W2[32][32], b2[32], w3[32], b3, in that order. */
-#define SHW_GATE_NPARAMS 1377
+#define SHW_GATE_NFEATURES 16
+#define SHW_GATE_NPARAMS 1633
 
 /* One uniform mesh (sec. 2: cells I_j of width dx; sec. 3: cells I_ij).
  * dim 1: nx cells on [x0, x1], ny must be 1.  dim 2: nx x ny cells.
@@ -145,34 +146,42 @@ shw_status shw_advance_to(shw_ctx *ctx, const double *T, long long max_steps,
 
 /* Per-cell gate flags for SHW_W_GATED (one byte per cell, non-zero = full
  * nonlinear reconstruction, zero = linear weights), for instance inst, from
- * host memory.  Overrides any flags computed by the learned gate until the
- * gate is evaluated again. */
+ * host memory.  Synchronising. */
 shw_status shw_set_flags(shw_ctx *ctx, int inst, const uint8_t *flags);
 
 /* ---- learned troubled-cell gate (an addition to the paper's method) ------
- * A small network scores each cell from 8 features of its own averages
- * (density and energy jumps to both neighbours, their difference, dx V);
- * cells scored below the threshold use the linear weights, the rest the full
- * SHWENO reconstruction.  The network runs in BF16 on the matrix cores with
- * FP32 accumulation; the scheme itself stays FP64. */
+ * A small network (16 -> 32 -> 32 -> 1, ReLU) scores each cell of a 1D Euler
+ * batch from 16 features of the data its reconstruction reads (sec. 2.3):
+ * per conservative component the signed shape of the jumps of the averages
+ * and of the neighbours' derivative averages, normalised by its size, and
+ * that size; and u / (|u| + c).  Cells whose probability of needing the
+ * nonlinear weights is below the threshold use the linear weights, the rest
+ * the full SHWENO reconstruction.  The network runs in BF16 on the matrix
+ * cores with FP32 accumulation; the scheme itself stays FP64.  Parameters:
+ * W1[32][16], b1[32], W2[32][32], b2[32], w3[32], b3, as FP32. */
 
 /* Load network parameters (host array of SHW_GATE_NPARAMS floats) into the
  * context for SHW_W_LEARNED.  Synchronising. */
 shw_status shw_gate_load(shw_ctx *ctx, const float *params);
 
 /* Training data from the method itself, 1D Euler batches: for every cell of
- * the batch (instances back to back) its 8 features (d_features, device,
- * [cells][8] floats) and its label (d_labels, device, one byte: 1 if the
- * characteristic nonlinear reconstruction gives the big stencil less than
- * 0.95 of its linear weight in some field).  Asynchronous. */
-shw_status shw_gate_data(shw_ctx *ctx, float *d_features, uint8_t *d_labels);
+ * the batch (instances back to back) its features (d_features, device,
+ * [cells][16] floats; per component c = rho, m, E with dl, dr the jumps of
+ * the averages, gm, gp = dx V of the left/right neighbour and
+ * S = |dl| + |dr| + |gm| + |gp|: (dl, dr, gm, gp) / S (0 if S < 1e-30) and
+ * log2(S^2 + 1e-12) / 32; last u / (|u| + c); FP32 from FP64 differences)
+ * and its label (d_labels, device, one byte: 1 if the cell's characteristic
+ * nonlinear reconstruction gives the big stencil less than level times its
+ * linear weight in some field).  level in (0, 1], else SHW_EINVAL.
+ * Asynchronous. */
+shw_status shw_gate_data(shw_ctx *ctx, double level, float *d_features, uint8_t *d_labels);
 
 /* Bytes of the packed (matrix-instruction layout) form of the network, and
  * the packing of host parameters into host memory. */
 size_t shw_gate_packed_bytes(void);
 shw_status shw_gate_pack(const float *params, void *packed);
 
-/* Logits of n samples (d_X: device [n][8] floats) with the packed network
+/* Logits of n samples (d_X: device [n][16] floats) with the packed network
  * d_packed (device copy of shw_gate_pack's output) on the matrix cores.
  * Asynchronous on hip_stream. */
 shw_status shw_mlp_logits(const float *d_X, int n, const void *d_packed, float *d_logits,

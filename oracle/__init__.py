@@ -118,9 +118,9 @@ def lib():
         L.orc_mlp_forward.argtypes = [ctypes.c_int, _D, _D, _D]
         L.orc_mlp_backward.argtypes = [ctypes.c_int, _D, _D, _D, ctypes.c_double, _D]
         L.orc_mlp_backward.restype = ctypes.c_double
-        L.orc_gate_features1d.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _D,
-                                          ctypes.c_int, _D]
-        L.orc_gate_label1d.argtypes = [P, ctypes.c_int, ctypes.c_double, _D, ctypes.c_int]
+        L.orc_gate_features1d.argtypes = [P, ctypes.c_int, ctypes.c_double, _D, ctypes.c_int, _D]
+        L.orc_gate_label1d.argtypes = [P, ctypes.c_int, ctypes.c_double, _D, ctypes.c_int,
+                                       ctypes.c_double]
         _lib = L
     return _lib
 
@@ -222,31 +222,36 @@ def grp_face(cfg: Config, dim: int, JL, JR) -> np.ndarray:
 
 # ---- learned gate ------------------------------------------------------------
 
-N_PARAMS = 32 * 8 + 32 + 32 * 32 + 32 + 32 + 1
+N_FEATURES = 16
+N_PARAMS = 32 * N_FEATURES + 32 + 32 * 32 + 32 + 32 + 1
 
 
-def gate_features1d(state, dx, bc=BC_PERIODIC):
-    """(n, 8) features of every cell of a 1D Euler state (2, 3, n)."""
+def gate_features1d(cfg: Config, state, dx):
+    """(n, 16) features of every cell of a 1D Euler state (2, 3, n)."""
     st = _f64(state)
     n = st.shape[-1]
-    out = np.zeros((n, 8))
-    f = np.zeros(8)
+    c = cfg.c()
+    out = np.zeros((n, N_FEATURES))
     for j in range(n):
-        lib().orc_gate_features1d(n, bc, dx, _p(st), j, _p(f))
+        f = np.zeros(N_FEATURES)
+        lib().orc_gate_features1d(ctypes.byref(c), n, dx, _p(st), j, _p(f))
         out[j] = f
     return out
 
 
-def gate_labels1d(cfg: Config, state, dx):
+def gate_labels1d(cfg: Config, state, dx, level=0.99, cells=None):
+    """Labels of cells 0..n-1 (or of the given indices, -1..n allowed)."""
     st = _f64(state)
     n = st.shape[-1]
     c = cfg.c()
-    return np.array([lib().orc_gate_label1d(ctypes.byref(c), n, dx, _p(st), j)
-                     for j in range(n)], dtype=np.uint8)
+    idx = range(n) if cells is None else cells
+    return np.array([lib().orc_gate_label1d(ctypes.byref(c), n, dx, _p(st), j, level)
+                     for j in idx], dtype=np.uint8)
 
 
 def mlp_forward(params, X):
     p, X = _f64(params), _f64(X)
+    assert p.size == N_PARAMS and X.ndim == 2 and X.shape[1] == N_FEATURES
     z = np.zeros(X.shape[0])
     lib().orc_mlp_forward(X.shape[0], _p(p), _p(X), _p(z))
     return z
@@ -255,6 +260,8 @@ def mlp_forward(params, X):
 def mlp_backward(params, X, y, pos_weight=1.0):
     """Mean weighted BCE of sigmoid(logits) and its gradient (FP64)."""
     p, X, y = _f64(params), _f64(X), _f64(y)
+    assert p.size == N_PARAMS and X.ndim == 2 and X.shape[1] == N_FEATURES
+    assert y.shape == (X.shape[0],)
     g = np.zeros(N_PARAMS)
     loss = lib().orc_mlp_backward(X.shape[0], _p(p), _p(X), _p(y), pos_weight, _p(g))
     return loss, g

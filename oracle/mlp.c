@@ -8,21 +8,22 @@
  * full nonlinear reconstruction (sec. 2.3) is needed or the linear weights
  * (the big-stencil quartic alone) suffice.
  *
- * Features of a cell (8, single precision in the GPU code): for each of two
- * quantities q (1D Euler: density and total energy; 2D Euler: density in x
- * and y, energy in x and y), with dl, dr the jumps of the cell averages to
- * the left/right neighbour, log2 of (dl^2 + d), (dr^2 + d) and either
- * ((dr - dl)^2 + d) and ((dx V)^2 + d) (1D) or the same two jumps in the other
- * direction (2D, then the quantities are density and energy), scaled by
- * 1/32; d = 1e-12 keeps logs finite.
+ * Features of a 1D Euler cell j (16, single precision in the GPU code), from
+ * exactly the data its reconstruction uses (cells j-1, j, j+1 with the
+ * boundary conditions' ghost cells): for each conservative component c, with
+ * dl = W_j - W_{j-1}, dr = W_{j+1} - W_j, gm = dx V_{j-1}, gp = dx V_{j+1}
+ * and S = |dl| + |dr| + |gm| + |gp|,
+ *   f[5c .. 5c+3] = (dl, dr, gm, gp) / S   (0 if S < 1e-30),
+ *   f[5c+4]       = log2(S^2 + 1e-12) / 32;
+ * and f[15] = u / (|u| + c) at cell j (0 if |u| + c = 0), which sets the
+ * characteristic projection.
  *
- * Label of a cell: 1 ("troubled") if the characteristic nonlinear
- * reconstruction of the cell gives the big quartic a weight below (1 - 0.05)
- * of its linear weight in any field (1D: along x; 2D: along x from (W, V) or
- * along y from (W, Y)).
+ * Label of a cell at level L: 1 ("troubled") if the characteristic nonlinear
+ * reconstruction of the cell gives the big quartic a weight below L times its
+ * linear weight in some field.
  *
- * Network: 8 -> 32 (ReLU) -> 32 (ReLU) -> 1 (logit); parameters in one array
- * W1[32][8], b1[32], W2[32][32], b2[32], w3[32], b3 (1377 values).
+ * Network: 16 -> 32 (ReLU) -> 32 (ReLU) -> 1 (logit); parameters in one array
+ * W1[32][16], b1[32], W2[32][32], b2[32], w3[32], b3 (1633 values).
  * Loss: weighted binary cross-entropy on sigmoid(logit), mean over samples.
  */
 #include <math.h>
@@ -31,44 +32,37 @@
 
 void orc_euler_eigen(double gamma, int dim, int dir, const double *W,
                      double *lam, double *R, double *L);
+void orc_cell1d(const orc_cfg *cfg, int n, const double *st, int j, double *W, double *V);
 
 #define H 32
-#define NF 8
+#define NF 16
 #define NPAR (H * NF + H + H * H + H + H + 1)
 
-static double logfeat(double x) { return log2(x + 1e-12) / 32.0; }
-
-/* features of cell j of a 1D Euler state (periodic or transmissive ghosts,
- * as the sweep's boundary conditions give them) */
-void orc_gate_features1d(int n, int bc, double dx, const double *st, int j, double f[NF])
+/* features of cell j of a 1D Euler state */
+void orc_gate_features1d(const orc_cfg *cfg, int n, double dx, const double *st, int j,
+                         double f[NF])
 {
     const int m = 3;
-    int jm = j - 1, jp = j + 1;
-    if (bc == ORC_BC_PERIODIC) {
-        jm = (jm + n) % n;
-        jp = jp % n;
-    } else {
-        if (jm < 0) jm = 0;
-        if (jp >= n) jp = n - 1;
+    double W[3][3], V[3][3];
+    for (int l = 0; l < 3; ++l) orc_cell1d(cfg, n, st, j - 1 + l, W[l], V[l]);
+    for (int c = 0; c < m; ++c) {
+        double d[4] = {W[1][c] - W[0][c], W[2][c] - W[1][c], dx * V[0][c], dx * V[2][c]};
+        double S = fabs(d[0]) + fabs(d[1]) + fabs(d[2]) + fabs(d[3]);
+        for (int k = 0; k < 4; ++k) f[5 * c + k] = S >= 1e-30 ? d[k] / S : 0.0;
+        f[5 * c + 4] = log2(S * S + 1e-12) / 32.0;
     }
-    const int qs[2] = {0, 2};          /* density, energy */
-    for (int k = 0; k < 2; ++k) {
-        int c = qs[k];
-        double a0 = st[c * n + j], am = st[c * n + jm], ap = st[c * n + jp];
-        double dl = a0 - am, dr = ap - a0;
-        double b = dx * st[(m + c) * n + j];
-        f[4 * k + 0] = logfeat(dl * dl);
-        f[4 * k + 1] = logfeat(dr * dr);
-        f[4 * k + 2] = logfeat((dr - dl) * (dr - dl));
-        f[4 * k + 3] = logfeat(b * b);
-    }
+    double rho = W[1][0], u = W[1][1] / rho;
+    double p = (cfg->gamma - 1.0) * (W[1][2] - 0.5 * rho * u * u);
+    double a2 = cfg->gamma * p / rho;
+    double den = fabs(u) + sqrt(a2 > 0.0 ? a2 : 0.0);
+    f[15] = den > 0.0 ? u / den : 0.0;
 }
 
-/* 1 if any characteristic field's big-stencil weight falls below 0.95 of
+/* 1 if a characteristic field's big-stencil weight falls below level times
  * its linear weight (data: averages and dx-scaled derivative averages of
  * cells -1, 0, +1 along one direction; dim/dir select the eigenvectors) */
 static int troubled_line(const orc_cfg *cfg, int dim, int dir, const double W[3][4],
-                         const double B[2][4])
+                         const double B[2][4], double level)
 {
     int m = orc_ncomp(cfg->eq, dim);
     double lam[4], R[16], L[16];
@@ -84,28 +78,21 @@ static int troubled_line(const orc_cfg *cfg, int dim, int dir, const double W[3]
             for (int c = 0; c < m; ++c) b[l] += L[s * m + c] * B[l][c];
         }
         orc_weights(cfg, a, b, w);
-        if (w[0] < 0.95 * cfg->lin_w[0]) return 1;
+        if (w[0] < level * cfg->lin_w[0]) return 1;
     }
     return 0;
 }
 
-int orc_gate_label1d(const orc_cfg *cfg, int n, double dx, const double *st, int j)
+int orc_gate_label1d(const orc_cfg *cfg, int n, double dx, const double *st, int j,
+                     double level)
 {
-    const int m = 3;
-    double W[3][4], B[2][4];
-    for (int l = 0; l < 3; ++l) {
-        int jj = j - 1 + l;
-        int zero_v = 0;
-        if (jj < 0 || jj >= n) {
-            if (cfg->bc[0] == ORC_BC_PERIODIC) jj = (jj + n) % n;
-            else { jj = jj < 0 ? 0 : n - 1; zero_v = 1; }
-        }
-        for (int c = 0; c < m; ++c) W[l][c] = st[c * n + jj];
-        if (l != 1)
-            for (int c = 0; c < m; ++c)
-                B[l / 2][c] = zero_v ? 0.0 : dx * st[(m + c) * n + jj];
+    double W[3][4], V[3][4], B[2][4];
+    for (int l = 0; l < 3; ++l) orc_cell1d(cfg, n, st, j - 1 + l, W[l], V[l]);
+    for (int c = 0; c < 3; ++c) {
+        B[0][c] = dx * V[0][c];
+        B[1][c] = dx * V[2][c];
     }
-    return troubled_line(cfg, 1, 0, W, B);
+    return troubled_line(cfg, 1, 0, W, B, level);
 }
 
 /* forward pass; h1, h2 (32 each) may be NULL */
@@ -131,7 +118,7 @@ double orc_mlp_logit(const double *p, const double x[NF], double *h1, double *h2
     return z;
 }
 
-/* logits of n samples X[n][8] */
+/* logits of n samples X[n][NF] */
 void orc_mlp_forward(int n, const double *p, const double *X, double *z)
 {
     for (int s = 0; s < n; ++s) z[s] = orc_mlp_logit(p, X + s * NF, NULL, NULL);

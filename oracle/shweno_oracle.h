@@ -123,12 +123,16 @@ int orc_advance2d(const orc_cfg *cfg, int nx, int ny, double dx, double dy,
 
 /* ---- learned gate (not part of the paper's method) ---------------------- */
 
-/* 8 features of cell j of a 1D Euler state; bc: boundary kind of both ends */
-void orc_gate_features1d(int n, int bc, double dx, const double *st, int j, double f[8]);
-/* 1 if the cell's nonlinear weights leave the big stencil below 0.95 of its
- * linear weight in some characteristic field */
-int orc_gate_label1d(const orc_cfg *cfg, int n, double dx, const double *st, int j);
-/* MLP 8-32-32-1: logits of n samples, and mean weighted BCE with gradient */
+/* 16 features of cell j of a 1D Euler state (ghosts by cfg's boundary
+ * conditions) */
+void orc_gate_features1d(const orc_cfg *cfg, int n, double dx, const double *st, int j,
+                         double f[16]);
+/* 1 if the nonlinear weights of cell j (-1..n: ghosts by the boundary
+ * conditions) leave the big stencil below level times its linear weight in
+ * some characteristic field */
+int orc_gate_label1d(const orc_cfg *cfg, int n, double dx, const double *st, int j,
+                     double level);
+/* MLP 16-32-32-1: logits of n samples, and mean weighted BCE with gradient */
 void orc_mlp_forward(int n, const double *params, const double *X, double *logits);
 double orc_mlp_backward(int n, const double *params, const double *X, const double *y,
                         double pos_weight, double *grad);

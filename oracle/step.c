@@ -105,9 +105,9 @@ static int source_index(int bc, int n, int j)
     return j < 0 ? -1 - j : 2 * n - 1 - j;   /* reflective: mirror */
 }
 
-/* averages of cell j (W: value, V: x-derivative), ghosts by the BCs */
-static void cell1d(const orc_cfg *cfg, int n, const double *st, int j,
-                   double *W, double *V)
+/* averages of cell j (W: value, V: x-derivative), ghosts by the BCs
+ * (also used by the gate's features and labels) */
+void orc_cell1d(const orc_cfg *cfg, int n, const double *st, int j, double *W, double *V)
 {
     int m = orc_ncomp(cfg->eq, 1);
     int bc = j < 0 ? cfg->bc[0] : cfg->bc[1];
@@ -141,7 +141,7 @@ static void recon_cell1d(const orc_cfg *cfg, int n, double dx, const double *st,
 {
     int m = orc_ncomp(cfg->eq, 1);
     double W[3][4], V[3][4];
-    for (int l = 0; l < 3; ++l) cell1d(cfg, n, st, j - 1 + l, W[l], V[l]);
+    for (int l = 0; l < 3; ++l) orc_cell1d(cfg, n, st, j - 1 + l, W[l], V[l]);
     int bc = j < 0 ? cfg->bc[0] : cfg->bc[1];
     int full = full_recon(cfg, flags, source_index(bc, n, j));
     if (cfg->eq == ORC_EULER && cfg->charwise && full) {

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(_HERE, "libshweno.so")
 ADVECTION, BURGERS, EULER = 0, 1, 2
 BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE = 0, 1, 2
 W_NONLINEAR, W_LINEAR, W_GATED, W_LEARNED = 0, 1, 2, 3
-GATE_NPARAMS = 1377
+GATE_NFEATURES = 16
+GATE_NPARAMS = 1633
 STATUS = {0: "SHW_OK", -1: "SHW_EINVAL", -2: "SHW_ENOMEM", -3: "SHW_EDEVICE",
           -4: "SHW_ENONPHYS", -5: "SHW_ESTATE"}
 
@@ -91,7 +92,7 @@ def lib():
         L.shw_instance_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
         FP = ctypes.POINTER(ctypes.c_float)
         L.shw_gate_load.argtypes = [vp, FP]
-        L.shw_gate_data.argtypes = [vp, vp, vp]
+        L.shw_gate_data.argtypes = [vp, ctypes.c_double, vp, vp]
         L.shw_gate_packed_bytes.restype = ctypes.c_size_t
         L.shw_gate_pack.argtypes = [FP, vp]
         L.shw_mlp_logits.argtypes = [vp, ctypes.c_int, vp, vp, vp]
@@ -133,9 +134,10 @@ def gate_pack(params) -> np.ndarray:
 
 
 def mlp_logits(X, packed):
-    """Logits of the samples X (cuda float32 [n, 8]) with a packed network
+    """Logits of the samples X (cuda float32 [n, 16]) with a packed network
     (cuda uint8 tensor), on the matrix cores."""
     import torch
+    assert X.dtype == torch.float32 and X.is_contiguous() and X.shape[1:] == (GATE_NFEATURES,)
     n = X.shape[0]
     out = torch.empty(n, dtype=torch.float32, device=X.device)
     _check_free(lib().shw_mlp_logits(_vp(X), n, _vp(packed), _vp(out), _stream_ptr()), "mlp_logits")
@@ -145,6 +147,8 @@ def mlp_logits(X, packed):
 def mlp_grad(X, y, params, pos_weight=1.0):
     """(loss, grad) of the weighted BCE on cuda tensors (FP32)."""
     import torch
+    assert X.dtype == torch.float32 and X.is_contiguous() and X.shape[1:] == (GATE_NFEATURES,)
+    assert y.dtype == torch.float32 and y.shape == (X.shape[0],) and params.numel() == GATE_NPARAMS
     g = torch.empty(GATE_NPARAMS, dtype=torch.float32, device=X.device)
     loss = torch.empty(1, dtype=torch.float32, device=X.device)
     _check_free(lib().shw_mlp_grad(_vp(X), _vp(y), X.shape[0], _vp(params), pos_weight,
@@ -264,14 +268,16 @@ class Solver:
         assert p.size == GATE_NPARAMS
         self._check(lib().shw_gate_load(self.ctx, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
 
-    def gate_data(self):
-        """(features [cells, 8] float32, labels [cells] uint8) cuda tensors for
-        every cell of the (1D Euler) batch in its current state."""
+    def gate_data(self, level=0.99):
+        """(features [cells, 16] float32, labels [cells] uint8) cuda tensors
+        for every cell of the (1D Euler) batch in its current state; a label
+        is 1 where the cell's quartic keeps less than level times its linear
+        weight."""
         torch = self.torch
         cells = sum(m.nx * m.ny for m in self.meshes)
-        f = torch.empty((cells, 8), dtype=torch.float32, device=self.device)
+        f = torch.empty((cells, GATE_NFEATURES), dtype=torch.float32, device=self.device)
         lab = torch.empty(cells, dtype=torch.uint8, device=self.device)
-        self._check(lib().shw_gate_data(self.ctx, _vp(f), _vp(lab)))
+        self._check(lib().shw_gate_data(self.ctx, float(level), _vp(f), _vp(lab)))
         return f, lab
 
     def set_flags(self, i, flags):

@@ -14,23 +14,27 @@ constexpr int TB = 128;          // samples per training block
 
 // features and label of every cell (grid: cells x instances)
 __global__ void __launch_bounds__(256) gate_data1d_kernel(const Inst1D *inst, const double *state,
-                                                          DevParams P, float *feat, uint8_t *label)
+                                                          DevParams P, double level, float *feat,
+                                                          uint8_t *label)
 {
     constexpr int M = 3;
     const Inst1D d = inst[blockIdx.y];
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= d.n) return;
     const double *src = state + d.off;
+    // three separately named cells, as in the sweep (a [3][M] array here was
+    // packed into one vector whose ghost-branch merge gave wrong derivative
+    // averages at the first cell)
     double Wm[M], Vm[M], W0[M], V0[M], Wp[M], Vp[M];
     load_cell<EULER, M>(src, d.n, j - 1, d.bc_lo, d.bc_hi, Wm, Vm);
     load_cell<EULER, M>(src, d.n, j, d.bc_lo, d.bc_hi, W0, V0);
     load_cell<EULER, M>(src, d.n, j + 1, d.bc_lo, d.bc_hi, Wp, Vp);
-    float f[8];
-    gate_features1d(Wm, W0, Wp, V0, d.dx, f);
+    float f[GATE_NF];
+    gate_features1d(Wm, W0, Wp, Vm, Vp, d.dx, P.gamma, f);
     const long long o = d.cell_off + j;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) feat[o * 8 + k] = f[k];
-    label[o] = (uint8_t)gate_label1d<M>(Wm, W0, Wp, Vm, Vp, d.dx, P);
+    for (int k = 0; k < GATE_NF; ++k) feat[o * GATE_NF + k] = f[k];
+    label[o] = (uint8_t)gate_label1d<M>(Wm, W0, Wp, Vm, Vp, d.dx, P, level);
 }
 
 // logits of n samples (one wave per 64 samples; all lanes take part)
@@ -39,9 +43,9 @@ __global__ void __launch_bounds__(256) mlp_logits_kernel(const float *X, int n, 
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x % 64;
-    float f[8];
+    float f[GATE_NF];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) f[k] = i < n ? X[(long long)i * 8 + k] : 0.0f;
+    for (int k = 0; k < GATE_NF; ++k) f[k] = i < n ? X[(long long)i * GATE_NF + k] : 0.0f;
     const GateLane g = G[lane];
     const float z = gate_wave_logit(f, g);
     if (i < n) logits[i] = z;
@@ -62,26 +66,26 @@ __global__ void __launch_bounds__(TB) mlp_grad_kernel(const float *X, const floa
                                                       const float *p, float pos_w, float *grad,
                                                       float *loss)
 {
-    __shared__ float sx[TB][8];
+    __shared__ float sx[TB][GATE_NF];
     __shared__ float sh1[TB][GATE_H + 1];
     __shared__ float sd1[TB][GATE_H + 1];
     __shared__ float sd2[TB][GATE_H + 1];
     __shared__ float sh2[TB][GATE_H + 1];
     __shared__ float sdz[TB];
-    const float *W1 = p, *b1 = W1 + GATE_H * 8, *W2 = b1 + GATE_H, *b2 = W2 + GATE_H * GATE_H;
+    const float *W1 = p, *b1 = W1 + GATE_H * GATE_NF, *W2 = b1 + GATE_H, *b2 = W2 + GATE_H * GATE_H;
     const float *w3 = b2 + GATE_H, *b3 = w3 + GATE_H;
     const int t = threadIdx.x;
     const long long i = (long long)blockIdx.x * TB + t;
     const bool ok = i < n;
-    float x[8];
+    float x[GATE_NF];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) x[k] = ok ? X[i * 8 + k] : 0.0f;
+    for (int k = 0; k < GATE_NF; ++k) x[k] = ok ? X[i * GATE_NF + k] : 0.0f;
     float h1[GATE_H], h2[GATE_H];
 #pragma unroll
     for (int r = 0; r < GATE_H; ++r) {
         float s = b1[r];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) s += W1[r * 8 + k] * x[k];
+        for (int k = 0; k < GATE_NF; ++k) s += W1[r * GATE_NF + k] * x[k];
         h1[r] = fmaxf(s, 0.0f);
     }
     float z = b3[0];
@@ -113,10 +117,10 @@ __global__ void __launch_bounds__(TB) mlp_grad_kernel(const float *X, const floa
         sd2[t][k] = d2[k];
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) sx[t][k] = x[k];
+    for (int k = 0; k < GATE_NF; ++k) sx[t][k] = x[k];
     sdz[t] = dz;
     __syncthreads();
-    float *gW1 = grad, *gb1 = gW1 + GATE_H * 8, *gW2 = gb1 + GATE_H, *gb2 = gW2 + GATE_H * GATE_H;
+    float *gW1 = grad, *gb1 = gW1 + GATE_H * GATE_NF, *gW2 = gb1 + GATE_H, *gb2 = gW2 + GATE_H * GATE_H;
     float *gw3 = gb2 + GATE_H, *gb3 = gw3 + GATE_H;
     // dW2[r][k] = sum_s d2[s][r] h1[s][k]: 1024 entries, 8 per thread
     for (int e = t; e < GATE_H * GATE_H; e += TB) {
@@ -125,8 +129,8 @@ __global__ void __launch_bounds__(TB) mlp_grad_kernel(const float *X, const floa
         for (int q = 0; q < TB; ++q) s += sd2[q][r] * sh1[q][k];
         atomicAdd(&gW2[e], s);
     }
-    for (int e = t; e < GATE_H * 8; e += TB) {
-        const int r = e / 8, k = e % 8;
+    for (int e = t; e < GATE_H * GATE_NF; e += TB) {
+        const int r = e / GATE_NF, k = e % GATE_NF;
         float s = 0.0f;
         for (int q = 0; q < TB; ++q) s += sd1[q][r] * sx[q][k];
         atomicAdd(&gW1[e], s);
@@ -174,10 +178,11 @@ __global__ void adam_kernel(float *p, const float *g, float *m, float *v, int n,
 } // namespace
 
 hipError_t launch_gate_data1d(const Inst1D *inst, int n_inst, int max_n, const double *state,
-                              const DevParams &P, float *feat, uint8_t *label, hipStream_t st)
+                              const DevParams &P, double level, float *feat, uint8_t *label,
+                              hipStream_t st)
 {
     dim3 grid((max_n + 255) / 256, n_inst);
-    gate_data1d_kernel<<<grid, 256, 0, st>>>(inst, state, P, feat, label);
+    gate_data1d_kernel<<<grid, 256, 0, st>>>(inst, state, P, level, feat, label);
     return hipGetLastError();
 }
 

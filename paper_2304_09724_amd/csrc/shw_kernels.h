@@ -82,7 +82,8 @@ hipError_t launch_step2d(int eq, const Step2D &S, const DevParams &P, int fixed,
 hipError_t launch_settle2d(const Step2D &S, int m, hipStream_t stream);
 
 hipError_t launch_gate_data1d(const Inst1D *inst, int n_inst, int max_n, const double *state,
-                              const DevParams &P, float *feat, uint8_t *label, hipStream_t stream);
+                              const DevParams &P, double level, float *feat, uint8_t *label,
+                              hipStream_t stream);
 hipError_t launch_mlp_logits(const float *X, int n, const GateLane *G, float *logits,
                              hipStream_t stream);
 hipError_t launch_mlp_grad(const float *X, const float *y, int n, const float *p, float pos_w,

@@ -26,6 +26,7 @@ struct DevParams {
     double cfl;
     double eps;
     double g1, g2, g3;   // linear weights: big quartic, left linear, right linear
+    double inv_g1;       // 1 / g1
     int charwise;
     int weights;
 };
@@ -76,9 +77,12 @@ SHW_HD void nonlinear_weights(const R c[5], R am, R a0, R ap, const DevParams &P
     const R b2 = dl * dl, b3 = dr * dr;
     R tau = 0.5 * (fabs(b1 - b2) + fabs(b1 - b3));
     tau = tau * tau;
-    const R w1 = P.g1 * (1.0 + tau / (b1 + P.eps));
-    const R w2 = P.g2 * (1.0 + tau / (b2 + P.eps));
-    const R w3 = P.g3 * (1.0 + tau / (b3 + P.eps));
+    // w_l = g_l (d_l + tau) / d_l with d_l = b_l + eps, normalised: over the
+    // common denominator d1 d2 d3 a single division remains
+    const R d1 = b1 + P.eps, d2 = b2 + P.eps, d3 = b3 + P.eps;
+    const R w1 = P.g1 * (d1 + tau) * (d2 * d3);
+    const R w2 = P.g2 * (d2 + tau) * (d1 * d3);
+    const R w3 = P.g3 * (d3 + tau) * (d1 * d2);
     const R inv = 1.0 / (w1 + w2 + w3);
     w[0] = w1 * inv;
     w[1] = w2 * inv;
@@ -90,7 +94,7 @@ SHW_HD void nonlinear_weights(const R c[5], R am, R a0, R ap, const DevParams &P
 template <class R>
 SHW_HD void combine(R c[5], R am, R a0, R ap, const R w[3], const DevParams &P)
 {
-    const R f = w[0] / P.g1;
+    const R f = w[0] * P.inv_g1;
     const R dl = a0 - am, dr = ap - a0;
     c[0] = f * (c[0] - (P.g2 + P.g3) * a0) + (w[1] + w[2]) * a0;
     c[1] = f * (c[1] - P.g2 * dl - P.g3 * dr) + w[1] * dl + w[2] * dr;
@@ -142,7 +146,7 @@ SHW_HD void euler_eigen(const Re *W, double gamma, Re R[][NComp<EULER, DIM>::M],
         const Re c2 = gamma * p * ir;
         const Re c = sqrt(c2), ic = 1.0 / c;
         const Re H = (W[2] + p) * ir;
-        const Re b1 = (gamma - 1.0) / c2, b2 = 0.5 * b1 * u * u;
+        const Re b1 = (gamma - 1.0) * (ic * ic), b2 = 0.5 * b1 * u * u;
         R[0][0] = 1.0;       R[0][1] = 1.0;         R[0][2] = 1.0;
         R[1][0] = u - c;     R[1][1] = u;           R[1][2] = u + c;
         R[2][0] = H - u * c; R[2][1] = 0.5 * u * u; R[2][2] = H + u * c;
@@ -157,7 +161,7 @@ SHW_HD void euler_eigen(const Re *W, double gamma, Re R[][NComp<EULER, DIM>::M],
         const Re c2 = gamma * p * ir;
         const Re c = sqrt(c2), ic = 1.0 / c;
         const Re H = (W[3] + p) * ir;
-        const Re b1 = (gamma - 1.0) / c2, b2 = 0.5 * b1 * q2;
+        const Re b1 = (gamma - 1.0) * (ic * ic), b2 = 0.5 * b1 * q2;
         // normal (n) and tangential (s) velocity and momentum slots
         const Re un = DIR == 0 ? u : v, us = DIR == 0 ? v : u;
         constexpr int N = DIR == 0 ? 1 : 2, T = DIR == 0 ? 2 : 1;
@@ -210,7 +214,13 @@ SHW_HD void hllc_state(const R *WL, const R *WR, double gamma, R *Ws)
     const R rl = WL[0], rr = WR[0];
     const R irl = 1.0 / rl, irr = 1.0 / rr;
     const R ul = WL[1] * irl, ur = WR[1] * irr;
-    const R pl = pressure<DIM>(WL, gamma), pr = pressure<DIM>(WR, gamma);
+    R kl = WL[1] * ul, kr = WR[1] * ur;                   // rho |u|^2
+    if constexpr (DIM == 2) {
+        kl = kl + WL[2] * (WL[2] * irl);
+        kr = kr + WR[2] * (WR[2] * irr);
+    }
+    const R pl = (gamma - 1.0) * (WL[M - 1] - 0.5 * kl);
+    const R pr = (gamma - 1.0) * (WR[M - 1] - 0.5 * kr);
     const R cl = sqrt(gamma * pl * irl), cr = sqrt(gamma * pr * irr);
     const R SL = fmin(ul - cl, ur - cr);
     const R SR = fmax(ul + cl, ur + cr);
@@ -228,13 +238,14 @@ SHW_HD void hllc_state(const R *WL, const R *WR, double gamma, R *Ws)
     }
     const bool left = 0.0 <= Ss;
     const R *WK = left ? WL : WR;
-    const R rk = left ? rl : rr, uk = left ? ul : ur, pk = left ? pl : pr;
+    const R uk = left ? ul : ur, pk = left ? pl : pr;
     const R SK = left ? SL : SR, mk = left ? ml : mr;
+    const R irk = left ? irl : irr;
     const R f = mk / (SK - Ss);
     Ws[0] = f;
     Ws[1] = f * Ss;
-    if constexpr (DIM == 2) Ws[2] = f * (WK[2] / rk);
-    Ws[M - 1] = f * (WK[M - 1] / rk + (Ss - uk) * (Ss + pk / mk));
+    if constexpr (DIM == 2) Ws[2] = f * (WK[2] * irk);
+    Ws[M - 1] = f * (WK[M - 1] * irk + (Ss - uk) * (Ss + pk / mk));
 }
 
 // Upwind solution at x/t = 0 of a linear Riemann problem with speed lam; a

@@ -178,6 +178,7 @@ shw_status shw_create(const shw_mesh *meshes, int n_inst, const shw_params *para
     dp.g1 = params->lin_w[0];
     dp.g2 = params->lin_w[1];
     dp.g3 = params->lin_w[2];
+    dp.inv_g1 = 1.0 / params->lin_w[0];
     dp.charwise = params->charwise;
     dp.weights = params->weights;
 
@@ -536,21 +537,31 @@ static unsigned short host_bf16(float f)
     return (unsigned short)(u >> 16);
 }
 
+static_assert(GATE_NPAR == SHW_GATE_NPARAMS && GATE_NF == SHW_GATE_NFEATURES,
+              "gate sizes of the header and the kernels differ");
+static_assert(sizeof(GateLane) == 256, "packed gate lane is 256 bytes");
+
 size_t shw_gate_packed_bytes(void) { return 64 * sizeof(GateLane); }
 
 shw_status shw_gate_pack(const float *p, void *packed)
 {
     if (!p || !packed) return SHW_EINVAL;
-    const float *W1 = p, *b1 = W1 + GATE_H * 8, *W2 = b1 + GATE_H, *b2 = W2 + GATE_H * GATE_H;
+    const float *W1 = p, *b1 = W1 + GATE_H * GATE_NF, *W2 = b1 + GATE_H, *b2 = W2 + GATE_H * GATE_H;
     const float *w3 = b2 + GATE_H, *b3 = w3 + GATE_H;
     GateLane *out = static_cast<GateLane *>(packed);
     std::memset(out, 0, 64 * sizeof(GateLane));
     for (int lane = 0; lane < 64; ++lane) {
         GateLane &L = out[lane];
         const int r = lane % 32, h = lane / 32;
-        for (int e = 0; e < 4; ++e) {
-            L.w1[e] = (short)host_bf16(W1[r * 8 + 4 * h + e]);
-            for (int q = 0; q < 4; ++q) L.w2[q][e] = (short)host_bf16(W2[r * GATE_H + 8 * q + 4 * h + e]);
+        for (int i = 0; i < 4; ++i) {
+            // BF16 pair (elements 2i, 2i + 1) in one word, element 2i low
+            auto pair = [](float a, float b) {
+                return (unsigned)host_bf16(a) | ((unsigned)host_bf16(b) << 16);
+            };
+            L.w1[i] = pair(W1[r * GATE_NF + 8 * h + 2 * i], W1[r * GATE_NF + 8 * h + 2 * i + 1]);
+            for (int q = 0; q < 2; ++q)
+                L.w2[q][i] = pair(W2[r * GATE_H + gate_hidden(q, h, 2 * i)],
+                                  W2[r * GATE_H + gate_hidden(q, h, 2 * i + 1)]);
         }
         for (int v = 0; v < 16; ++v) {
             const int row = mfma_row(lane, v);
@@ -576,15 +587,17 @@ shw_status shw_gate_load(shw_ctx *c, const float *params)
     return s;
 }
 
-shw_status shw_gate_data(shw_ctx *c, float *d_features, uint8_t *d_labels)
+shw_status shw_gate_data(shw_ctx *c, double level, float *d_features, uint8_t *d_labels)
 {
     if (!c || !d_features || !d_labels) return SHW_EINVAL;
     if (c->dim != 1 || c->params.eq != SHW_EULER)
         return c->fail(SHW_EINVAL, "gate data: 1D Euler only");
+    if (!(level > 0.0 && level <= 1.0))
+        return c->fail(SHW_EINVAL, "gate data: label level must lie in (0, 1]");
     int max_n = 0;
     for (const auto &m : c->meshes) max_n = std::max(max_n, m.nx);
     return c->hip(launch_gate_data1d(c->at<Inst1D>(c->lay.inst), c->n_inst, max_n, c->state, c->dp,
-                                     d_features, d_labels, c->stream), "gate data");
+                                     level, d_features, d_labels, c->stream), "gate data");
 }
 
 shw_status shw_mlp_logits(const float *d_X, int n, const void *d_packed, float *d_logits,

@@ -35,8 +35,8 @@ __device__ __forceinline__ bool bad_state(const double *W, const DevParams &P)
 #pragma unroll
     for (int c = 0; c < M; ++c) bad |= !isfinite(W[c]);
     if constexpr (EQ == EULER) {
-        const double p = (P.gamma - 1.0) * (W[2] - 0.5 * W[1] * W[1] / W[0]);
-        bad |= !(W[0] > 0.0) || !(p > 0.0);
+        // p > 0  <=>  2 rho E > (rho u)^2 when rho > 0
+        bad |= !(W[0] > 0.0) || !(2.0 * W[0] * W[2] - W[1] * W[1] > 0.0);
     }
     return bad;
 }
@@ -55,13 +55,14 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
                                                double *__restrict__ dst, double dt,
                                                const DevParams &P,
                                                const uint8_t *__restrict__ flags,
-                                               const GateLane *gate, float gate_logit_min)
+                                               const u32x4 *gate, float gate_logit_min)
 {
     constexpr int M = NComp<EQ, 1>::M;
     const int lane = threadIdx.x % WAVE;
     const int wave = threadIdx.x / WAVE;
     const int n = d.n;
     const int nchunk = (n + CHUNK - 1) / CHUNK;
+    const double idx = 1.0 / d.dx, dt_dx = dt * idx;
     bool bad = false;
     for (int ch = wave; ch < nchunk; ch += BLOCK / WAVE) {
         const int j = ch * CHUNK + lane - 1;       // this lane's cell, -1..n+61
@@ -77,13 +78,16 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
         if constexpr (EQ == EULER) {
             if (P.weights == W_LEARNED) {
                 // the whole wave evaluates the network for its 64 cells
-                float f[8];
-                gate_features1d(Wm, W0, Wp, V0, d.dx, f);
-                full = gate_wave_logit(f, gate[lane]) >= gate_logit_min;
+                float f[GATE_NF];
+                gate_features1d(Wm, W0, Wp, Vm, Vp, d.dx, P.gamma, f);
+                full = gate_wave_logit(f, gate_lane_lds(gate, lane)) >= gate_logit_min;
             }
         }
         double lo[5][M], hi[5][M];
-        recon_cell<EQ, M>(Wm, W0, Wp, Vm, Vp, d.dx, full, P, lo, hi);
+        // one reconstruction path per wave: characteristic if any lane needs
+        // the nonlinear weights
+        const bool charpath = __any(full);
+        recon_cell<EQ, M>(Wm, W0, Wp, Vm, Vp, d.dx, idx, full, charpath, P, lo, hi);
         // right-edge jet of the left neighbour
         double prev[5][M];
 #pragma unroll
@@ -105,7 +109,7 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
         }
         if (lane >= 1 && lane <= CHUNK && j >= 0 && j < n) {
             double Wnew[M], Vnew[M];
-            update1d<M>(W0, Fh, Fn, We, Wn, dt / d.dx, 1.0 / d.dx, Wnew, Vnew);
+            update1d<M>(W0, Fh, Fn, We, Wn, dt_dx, idx, Wnew, Vnew);
 #pragma unroll
             for (int c = 0; c < M; ++c) {
                 dst[c * n + j] = Wnew[c];
@@ -123,13 +127,11 @@ __global__ void __launch_bounds__(BLOCK) loop1d_kernel(Loop1D Lp, DevParams P)
     constexpr int M = NComp<EQ, 1>::M;
     __shared__ int s_item;
     __shared__ double s_red[BLOCK / WAVE];
-    __shared__ GateLane s_gate[EQ == EULER ? WAVE : 1];
+    __shared__ u32x4 s_gate[EQ == EULER ? GATE_LDS_WORDS : 1];
     const int tid = threadIdx.x;
     if (EQ == EULER && P.weights == W_LEARNED) {
-        // the packed network, one slot per lane position, shared by the waves
-        const int words = (int)(sizeof(GateLane) / 4) * WAVE;
-        for (int e = tid; e < words; e += BLOCK)
-            reinterpret_cast<unsigned *>(s_gate)[e] = reinterpret_cast<const unsigned *>(Lp.gate)[e];
+        // the packed network, shared by the waves, transposed for the LDS
+        gate_to_lds(Lp.gate, s_gate, tid, BLOCK);
         __syncthreads();
     }
     for (;;) {

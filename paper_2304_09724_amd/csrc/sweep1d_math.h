@@ -41,17 +41,21 @@ __device__ __forceinline__ int load_cell(const double *__restrict__ base, int n,
 
 
 // Step 1: reconstruction of one cell; lo/hi receive d^a W/dx^a at the left
-// and right edge, a = 0..4.
+// and right edge, a = 0..4.  full: nonlinear weights, else the linear ones
+// (the big quartic alone).  charpath (Euler, characteristic reconstruction
+// on): work in characteristic fields; a cell with linear weights gets the
+// same polynomial either way (the big quartic is linear in its data), up to
+// rounding, so callers choose the path once for a whole wave and the cheap
+// component-wise form serves waves without nonlinear cells.
 template <int EQ, int M, class Re>
 SHW_HD void recon_cell(const Re Wm[M], const Re W0[M], const Re Wp[M], const Re Vm[M],
-                       const Re Vp[M], double dx, bool full, const DevParams &P,
-                       Re lo[5][M], Re hi[5][M])
+                       const Re Vp[M], double dx, double idx, bool full, bool charpath,
+                       const DevParams &P, Re lo[5][M], Re hi[5][M])
 {
-    const double idx = 1.0 / dx;
     double sc[5];
     sc[0] = 1.0; sc[1] = idx; sc[2] = idx * idx; sc[3] = sc[2] * idx; sc[4] = sc[2] * sc[2];
     if constexpr (EQ == EULER) {
-        if (full && P.charwise) {
+        if (charpath && P.charwise) {
             Re R[M][M], L[M][M], lam[M];
             euler_eigen<1, 0>(W0, P.gamma, R, L, lam);
             Re clo[M][5], chi[M][5];
@@ -66,10 +70,13 @@ SHW_HD void recon_cell(const Re Wm[M], const Re W0[M], const Re Wp[M], const Re 
                     bm += L[s][c] * Vm[c];
                     bp += L[s][c] * Vp[c];
                 }
-                Re q[5], w[3];
+                Re q[5];
                 big_quartic(am, a0, ap, Re(dx * bm), Re(dx * bp), q);
-                nonlinear_weights(q, am, a0, ap, P, w);
-                combine(q, am, a0, ap, w, P);
+                if (full) {
+                    Re w[3];
+                    nonlinear_weights(q, am, a0, ap, P, w);
+                    combine(q, am, a0, ap, w, P);
+                }
                 edge_derivs(q, clo[s], chi[s]);
             }
 #pragma unroll
@@ -267,9 +274,10 @@ SHW_HD R wave_speed(const R *W, const DevParams &P)
     if constexpr (EQ == ADV) return R(fabs(P.adv_a));
     else if constexpr (EQ == BURG) return fabs(W[0]);
     else {
-        const R u = W[1] / W[0];
+        const R ir = 1.0 / W[0];
+        const R u = W[1] * ir;
         const R p = (P.gamma - 1.0) * (W[2] - 0.5 * W[1] * u);
-        return fabs(u) + sqrt(P.gamma * p / W[0]);
+        return fabs(u) + sqrt(P.gamma * p * ir);
     }
 }
 

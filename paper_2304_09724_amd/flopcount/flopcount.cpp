@@ -66,7 +66,7 @@ static void euler1d(bool full, const char *name)
 {
     DevParams P{};
     P.gamma = 1.4; P.cfl = 0.9; P.eps = 1e-6;
-    P.g1 = 0.994; P.g2 = 0.003; P.g3 = 0.003;
+    P.g1 = 0.994; P.g2 = 0.003; P.g3 = 0.003; P.inv_g1 = 1.0 / 0.994;
     P.charwise = 1;
     P.weights = full ? W_NONLINEAR : W_LINEAR;
     constexpr int M = 3;
@@ -76,7 +76,7 @@ static void euler1d(bool full, const char *name)
     Cnt s = wave_speed<EULER>(W0, P);
     (void)s;
     Cnt lo[5][M], hi[5][M];
-    recon_cell<EULER, M>(Wm, W0, Wp, Vm, Vp, 0.01, full, P, lo, hi);
+    recon_cell<EULER, M>(Wm, W0, Wp, Vm, Vp, 0.01, 100.0, full, full, P, lo, hi);
     Cnt Fh[M], We[M];
     face1d<EULER, M>(hi, lo, 0.004, P, Fh, We);
     Cnt Wn[M], Vn[M];
@@ -92,7 +92,7 @@ static void euler2d(bool full, const char *name)
 {
     DevParams P{};
     P.gamma = 1.4; P.cfl = 0.9; P.eps = 1e-6;
-    P.g1 = 0.994; P.g2 = 0.003; P.g3 = 0.003;
+    P.g1 = 0.994; P.g2 = 0.003; P.g3 = 0.003; P.inv_g1 = 1.0 / 0.994;
     P.charwise = 1;
     P.weights = full ? W_NONLINEAR : W_LINEAR;
     constexpr int M = 4;

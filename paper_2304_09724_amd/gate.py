@@ -12,23 +12,28 @@ from __future__ import annotations
 import numpy as np
 
 from . import Mesh, Params, Solver, EULER, W_NONLINEAR, BC_PERIODIC, BC_TRANSMISSIVE, \
-    GATE_NPARAMS, mlp_adam, mlp_grad
+    GATE_NFEATURES, GATE_NPARAMS, mlp_adam, mlp_grad
 from . import workloads as WL
+
+# A cell is labelled troubled where its quartic keeps less than this fraction
+# of its linear weight in some characteristic field.
+LABEL_LEVEL = 0.999
 
 
 def init_params(seed: int = 0) -> np.ndarray:
     """He-initialised parameters (W1, b1, W2, b2, w3, b3)."""
     rng = np.random.default_rng(seed)
-    W1 = rng.normal(size=(32, 8)) * np.sqrt(2.0 / 8)
+    W1 = rng.normal(size=(32, GATE_NFEATURES)) * np.sqrt(2.0 / GATE_NFEATURES)
     W2 = rng.normal(size=(32, 32)) * np.sqrt(2.0 / 32)
     w3 = rng.normal(size=32) * np.sqrt(1.0 / 32)
     return np.concatenate([W1.ravel(), np.zeros(32), W2.ravel(), np.zeros(32), w3, [0.0]]
                           ).astype(np.float32)
 
 
-def collect(problems, times, device="cuda"):
-    """Features and labels of every cell of a 1D Euler batch, sampled at the
-    given times of plain runs.  problems: list of (mesh, state)."""
+def collect(problems, times, level=LABEL_LEVEL, device="cuda"):
+    """Features and labels (at the given level) of every cell of a 1D Euler
+    batch, sampled at the given times of plain runs.  problems: list of
+    (mesh, state)."""
     import torch
     meshes = [m for m, _ in problems]
     s = Solver(meshes, Params.make(eq=EULER, weights=W_NONLINEAR), device=device)
@@ -38,7 +43,7 @@ def collect(problems, times, device="cuda"):
     for t in times:
         if t > 0:
             s.advance_to(t, raise_nonphysical=False)
-        f, lab = s.gate_data()
+        f, lab = s.gate_data(level)
         ok = torch.isfinite(f).all(dim=1)
         feats.append(f[ok])
         labs.append(lab[ok])
@@ -56,7 +61,7 @@ def training_problems(seed: int = 7, count: int = 48):
     return probs
 
 
-def train(X, y, steps=600, lr=3e-3, pos_weight=4.0, seed=0, batch=16384, log=None):
+def train(X, y, steps=800, lr=3e-3, pos_weight=8.0, seed=0, batch=16384, log=None):
     """Adam on the library's kernels; returns (params as numpy, loss history)."""
     import torch
     dev = X.device

@@ -1,8 +1,9 @@
 """GPU tests of the learned troubled-cell gate: the BF16 matrix-core network
 against the FP64 oracle network, the FP32 training gradient against the
-oracle gradient, Adam, the features and labels the method generates, the
-gate's limits (all-full = plain, all-linear = linear weights), and a trained
-gate that keeps the plain method's error while passing smooth cells."""
+oracle gradient, Adam, the features and labels the method generates (all
+boundary kinds), the gate's limits (all-full = plain, all-linear = linear
+weights), and a trained gate that keeps the plain method's error and adds no
+oscillation while passing most cells as smooth."""
 import numpy as np
 import pytest
 import torch
@@ -28,19 +29,25 @@ def packed(params):
     return torch.from_numpy(S.gate_pack(params)).cuda()
 
 
+NF = S.GATE_NFEATURES
+# parameter blocks: W1[32][NF], b1, W2[32][32], b2, w3, b3
+OW1, OB1, OW2, OB2, OW3, OB3 = 0, 32 * NF, 32 * NF + 32, 32 * NF + 1056, 32 * NF + 1088, 32 * NF + 1120
+
+
 def test_matrix_core_layout_is_exact():
     """Weights and inputs chosen so that every product and every hidden value
     is exact in BF16/FP32: the network must reproduce the FP64 oracle
     exactly, which pins the operand and accumulator layouts."""
     rng = np.random.default_rng(0)
     p = np.zeros(S.GATE_NPARAMS, dtype=np.float32)
-    p[:256] = rng.choice([-1.0, 0.0, 1.0], size=256)
-    p[256:288] = rng.choice([-0.5, 0.0, 0.5], size=32)
-    p[288:1312] = rng.choice([-1.0, 0.0, 1.0], size=1024)
-    p[1312:1344] = rng.choice([-1.0, 0.0, 1.0], size=32)
-    p[1344:1376] = rng.choice([-0.25, 0.0, 0.5], size=32)
-    p[1376] = 0.75
-    X = rng.choice([0.0, 0.5, 1.0, 1.5, 2.0], size=(200, 8)).astype(np.float32)
+    p[OW1:OB1] = rng.choice([-1.0, 0.0, 1.0], size=OB1 - OW1)
+    p[OB1:OW2] = rng.choice([-0.5, 0.0, 0.5], size=32)
+    p[OW2:OB2] = rng.choice([-1.0, 0.0, 1.0], size=1024)
+    p[OB2:OW3] = rng.choice([-1.0, 0.0, 1.0], size=32)
+    p[OW3:OB3] = rng.choice([-0.25, 0.0, 0.5], size=32)
+    p[OB3] = 0.75
+    assert OB3 + 1 == S.GATE_NPARAMS
+    X = rng.choice([0.0, 0.5, 1.0, 1.5, 2.0], size=(200, NF)).astype(np.float32)
     z = S.mlp_logits(torch.from_numpy(X).cuda(), packed(p)).cpu().numpy()
     want = O.mlp_forward(p.astype(np.float64), X.astype(np.float64))
     np.testing.assert_allclose(z, want, rtol=0, atol=1e-5)
@@ -49,11 +56,11 @@ def test_matrix_core_layout_is_exact():
 def test_logits_match_oracle_within_bf16():
     rng = np.random.default_rng(1)
     p = GT.init_params(3)
-    X = rng.normal(size=(1000, 8)).astype(np.float32)
+    X = rng.normal(size=(1000, NF)).astype(np.float32)
     z = S.mlp_logits(torch.from_numpy(X).cuda(), packed(p)).cpu().numpy()
     pr = p.astype(np.float64).copy()
-    pr[:256] = bf16(p[:256])
-    pr[288:1312] = bf16(p[288:1312])
+    pr[OW1:OB1] = bf16(p[OW1:OB1])
+    pr[OW2:OB2] = bf16(p[OW2:OB2])
     want = O.mlp_forward(pr, bf16(X))
     # the only other rounding is the first hidden layer's BF16 input to layer 2
     assert np.abs(z - want).max() < 0.03 * (1 + np.abs(want).max())
@@ -62,7 +69,7 @@ def test_logits_match_oracle_within_bf16():
 def test_training_gradient_matches_oracle():
     rng = np.random.default_rng(2)
     p = GT.init_params(5)
-    X = rng.normal(size=(2000, 8)).astype(np.float32)
+    X = rng.normal(size=(2000, NF)).astype(np.float32)
     y = (rng.uniform(size=2000) < 0.2).astype(np.float32)
     loss, g = S.mlp_grad(torch.from_numpy(X).cuda(), torch.from_numpy(y).cuda(),
                          torch.from_numpy(p).cuda(), pos_weight=4.0)
@@ -84,25 +91,35 @@ def test_adam_step():
     np.testing.assert_allclose(pt.cpu().numpy(), want, rtol=1e-5, atol=1e-7)
 
 
-def test_features_and_labels_match_oracle():
-    insts = WL.riemann_batch_1d(count=4, seed=3, nmin=60, nmax=120)
-    meshes = [S.Mesh.line(d.n, d.x0, d.x1, S.BC_TRANSMISSIVE) for d in insts]
+@pytest.mark.parametrize("level", [0.99, GT.LABEL_LEVEL])
+def test_features_and_labels_match_oracle(level):
+    """Features (FP32 from FP64 data) and labels (exact) of every cell of a
+    batch with transmissive, periodic and reflective ends, ragged sizes."""
+    insts = WL.riemann_batch_1d(count=3, seed=3, nmin=60, nmax=130)
+    bcs = [S.BC_TRANSMISSIVE, S.BC_PERIODIC, S.BC_REFLECTIVE]
+    meshes = [S.Mesh.line(d.n, d.x0, d.x1, bc) for d, bc in zip(insts, bcs)]
+    meshes.append(S.Mesh.line(77, 0.0, 2.0, S.BC_PERIODIC))
+    states = [d.state() for d in insts] + [WL.density_wave_1d(77)]
     s = S.Solver(meshes, S.Params.make(eq=S.EULER))
-    for i, d in enumerate(insts):
-        s.set_state(i, d.state())
+    for i, st in enumerate(states):
+        s.set_state(i, st)
     s.advance_to(0.02)
-    f, lab = s.gate_data()
+    f, lab = s.gate_data(level)
     f, lab = f.cpu().numpy(), lab.cpu().numpy()
-    cfg = O.Config(eq=O.EULER, bc=(O.BC_TRANSMISSIVE,) * 4)
     off = 0
-    for i, d in enumerate(insts):
+    for i, m in enumerate(meshes):
+        n = m.nx
+        cfg = O.Config(eq=O.EULER, bc=(bcs[i] if i < 3 else S.BC_PERIODIC,) * 4)
         st = s.get_state(i)
-        fo = O.gate_features1d(st, d.dx, O.BC_TRANSMISSIVE)
-        lo = O.gate_labels1d(cfg, st, d.dx)
-        np.testing.assert_allclose(f[off:off + d.n], fo, rtol=0, atol=2e-6)
-        assert np.array_equal(lab[off:off + d.n], lo)
-        assert lo.any() and not lo.all()
-        off += d.n
+        dx = 2.0 / n if i == 3 else insts[i].dx
+        fo = O.gate_features1d(cfg, st, dx)
+        lo = O.gate_labels1d(cfg, st, dx, level)
+        np.testing.assert_allclose(f[off:off + n], fo, rtol=1e-6, atol=2e-6)
+        assert np.array_equal(lab[off:off + n], lo), i
+        if i < 3:
+            assert lo.any() and not lo.all()
+        off += n
+    assert off == f.shape[0]
 
 
 @pytest.mark.parametrize("b3,mode", [(40.0, S.W_NONLINEAR), (-40.0, S.W_LINEAR)])
@@ -112,7 +129,7 @@ def test_learned_gate_limits(b3, mode):
     linear-weight scheme (on the smooth density wave, which linear weights
     can run)."""
     p = np.zeros(S.GATE_NPARAMS, dtype=np.float32)
-    p[1376] = b3
+    p[OB3] = b3
     if b3 > 0:
         d = WL.riemann_batch_1d(count=1, seed=9, nmin=100, nmax=100)[0]
         m = [S.Mesh.line(d.n, d.x0, d.x1, S.BC_TRANSMISSIVE)]
@@ -140,23 +157,29 @@ def exact_rho(d, t, sub=16):
     return out.mean(axis=1)
 
 
-def extrema(r, range_):
-    d = np.diff(r)
-    big = np.abs(d) > 1e-6 * range_
-    s = np.sign(d[big])
-    return int((s[1:] != s[:-1]).sum())
+def total_variation(r):
+    return float(np.abs(np.diff(r)).sum())
+
+
+def envelope_excess(rg, rp):
+    """How far the gated solution leaves the plain solution's local 3-cell
+    min/max envelope (0 if it stays inside)."""
+    lo = np.minimum(np.minimum(rp[:-2], rp[1:-1]), rp[2:])
+    hi = np.maximum(np.maximum(rp[:-2], rp[1:-1]), rp[2:])
+    mid = rg[1:-1]
+    return float(max((mid - hi).max(), (lo - mid).max(), 0.0))
 
 
 def test_trained_gate_keeps_the_error_of_the_plain_method():
     X, y = GT.collect(GT.training_problems(), times=[0.0, 0.02, 0.06, 0.1, 0.14])
     assert 0.01 < float(y.mean()) < 0.5
-    params, hist = GT.train(X, y, steps=500)
+    params, hist = GT.train(X, y)
     assert hist[-1] < 0.5 * hist[0]
     # held-out problems from the batched workload's distribution
     val = WL.riemann_batch_1d(count=12, seed=1234, nmin=100, nmax=400)
     meshes = [S.Mesh.line(d.n, d.x0, d.x1, S.BC_TRANSMISSIVE) for d in val]
     plain = S.Solver(meshes, S.Params.make(eq=S.EULER))
-    gated = S.Solver(meshes, S.Params.make(eq=S.EULER, weights=S.W_LEARNED, gate_threshold=0.1))
+    gated = S.Solver(meshes, S.Params.make(eq=S.EULER, weights=S.W_LEARNED, gate_threshold=0.05))
     gated.gate_load(params)
     for i, d in enumerate(val):
         plain.set_state(i, d.state())
@@ -173,9 +196,24 @@ def test_trained_gate_keeps_the_error_of_the_plain_method():
         l1p.append(np.abs(rp - ex).mean())
         l1g.append(np.abs(rg - ex).mean())
         rng_ = ex.max() - ex.min()
-        assert extrema(rg, rng_) <= extrema(rp, rng_) + 2, i
+        # no new oscillations: no extra total variation, no overshoot beyond
+        # the plain solution's local envelope
+        assert total_variation(rg) <= 1.01 * total_variation(rp), i
+        assert envelope_excess(rg, rp) <= 1e-3 * rng_, i
     assert len(l1p) >= 8
     assert np.sum(l1g) <= 1.05 * np.sum(l1p)
-    # the gate must actually pass most cells as smooth
+    # the gate must actually pass most cells as smooth: over the training
+    # cells (5-10 % labelled troubled) and over the held-out states
     z = S.mlp_logits(X[:200000].contiguous(), packed(params)).cpu().numpy()
-    assert (1.0 / (1.0 + np.exp(-z)) < 0.1).mean() > 0.5
+    assert (1.0 / (1.0 + np.exp(-z)) < 0.05).mean() > 0.75
+    mid = S.Solver(meshes, S.Params.make(eq=S.EULER))
+    for i, d in enumerate(val):
+        mid.set_state(i, d.state())
+    mid.advance_to(0.07, raise_nonphysical=False)
+    fv, lv = mid.gate_data(GT.LABEL_LEVEL)
+    zv = S.mlp_logits(fv, packed(params)).cpu().numpy()
+    passed = 1.0 / (1.0 + np.exp(-zv)) < 0.05
+    assert passed.mean() > 0.75
+    # and passes few cells the label calls troubled
+    lv = lv.cpu().numpy().astype(bool)
+    assert (passed & lv).sum() <= 0.05 * lv.sum()
