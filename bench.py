@@ -103,8 +103,10 @@ def gated_leg(S, insts, states, meshes, init, args, plain_value, plain):
     params, hist = GT.train(X, y)
     train_s = time.perf_counter() - t0
     threshold = 0.05
+    every = 2
     g = S.Solver(meshes, S.Params.make(eq=S.EULER, cfl=0.9, weights=S.W_LEARNED,
-                                       gate_threshold=threshold), device="cuda:0")
+                                       gate_threshold=threshold, gate_every=every),
+                 device="cuda:0")
     g.gate_load(params)
     zeros = np.zeros(COUNT)
     T = np.full(COUNT, T_END)
@@ -139,6 +141,7 @@ def gated_leg(S, insts, states, meshes, init, args, plain_value, plain):
     smooth = float((z < np.log(threshold / (1 - threshold))).mean())
     return {"value": value, "unit": "cell-updates/s", "speedup_vs_plain": value / plain_value,
             "ms_per_step": wall / args.steps * 1e3, "gate_threshold": threshold,
+            "gate_every_steps": every,
             "l1_ratio_gated_over_plain": l1g / l1p, "l1_sample_instances": len(sample),
             "total_variation_ratio_gated_over_plain": tvg / tvp,
             "nonphysical_instances": int((~okg).sum()),

@@ -78,8 +78,13 @@ typedef struct {
  * reconstruct characteristic fields; weights: SHW_W_* — NONLINEAR is the
  * paper's SHWENO (sec. 2.3), LINEAR uses the linear weights everywhere, GATED
  * takes per-cell flags from shw_set_flags, LEARNED (1D Euler) evaluates the
- * learned gate in every step; gate_threshold (0 < t < 1): a cell whose gate
- * score sigmoid(logit) is >= t takes the full nonlinear reconstruction. */
+ * learned gate; gate_threshold (0 < t < 1): a cell whose gate score
+ * sigmoid(logit) is >= t takes the full nonlinear reconstruction;
+ * gate_every (LEARNED, 1..1024): the gate is evaluated at the first step of
+ * each call and then every gate_every steps of an instance; s steps after an
+ * evaluation a cell takes the nonlinear weights if any cell within 2s of it
+ * was flagged then (the distance the data of a reconstruction can travel in
+ * s steps).  LEARNED overwrites the per-cell flags of SHW_W_GATED. */
 typedef struct {
     int eq;
     int charwise;
@@ -90,6 +95,7 @@ typedef struct {
     double eps;
     double lin_w[3];
     double gate_threshold;
+    int gate_every;
 } shw_params;
 
 typedef struct shw_ctx shw_ctx;
@@ -98,7 +104,9 @@ typedef struct shw_ctx shw_ctx;
  * or parameters are invalid. */
 size_t shw_state_doubles(const shw_mesh *mesh, const shw_params *params);
 
-/* Bytes of device workspace shw_create needs for this batch, 0 if invalid. */
+/* Bytes of device workspace shw_create needs for this batch, 0 if invalid
+ * (meshes of different dimensions, Burgers outside 1D, the learned gate
+ * outside 1D Euler, or an invalid mesh or parameter set). */
 size_t shw_workspace_bytes(const shw_mesh *meshes, int n_inst, const shw_params *params);
 
 /* Create a context for n_inst instances (all with the same dim and params).

@@ -49,9 +49,11 @@ struct Loop1D {
     const double *dt_fixed;    // per instance fixed step (NULL: CFL mode)
     long long max_steps;       // per instance step limit for this launch
     InstState *ist;
-    const uint8_t *flags;      // per cell gate flags (GATED mode)
+    uint8_t *flags;            // per cell gate flags (read in GATED mode; LEARNED
+                               // writes them at gate steps, reads them in between)
     const GateLane *gate;      // packed network (LEARNED mode)
     float gate_logit_min;      // cells with logit >= this take the full reconstruction
+    int gate_every;            // LEARNED: evaluate the network every this many steps
 };
 
 // Launch parameters of one 2D step over a batch (all pointers device-side).

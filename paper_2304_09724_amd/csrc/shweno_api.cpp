@@ -28,7 +28,9 @@ bool valid_params(const shw_params *p)
     if (!p) return false;
     if (p->eq < SHW_ADVECTION || p->eq > SHW_EULER) return false;
     if (p->weights < SHW_W_NONLINEAR || p->weights > SHW_W_LEARNED) return false;
-    if (p->weights == SHW_W_LEARNED && !(p->gate_threshold > 0.0 && p->gate_threshold < 1.0))
+    if (p->weights == SHW_W_LEARNED &&
+        (!(p->gate_threshold > 0.0 && p->gate_threshold < 1.0) || p->gate_every < 1 ||
+         p->gate_every > 1024))
         return false;
     if (p->eq == SHW_EULER && !(p->gamma > 1.0)) return false;
     if (!(p->cfl > 0.0) || !(p->eps > 0.0)) return false;
@@ -138,11 +140,22 @@ size_t shw_state_doubles(const shw_mesh *mesh, const shw_params *params)
     return state_doubles(mesh, params->eq);
 }
 
+// a batch: valid meshes of one dimension, and an equation / weight mode the
+// library runs in that dimension
+static bool valid_batch(const shw_mesh *meshes, int n_inst, const shw_params *params)
+{
+    if (!meshes || n_inst < 1 || !valid_params(params)) return false;
+    for (int i = 0; i < n_inst; ++i)
+        if (!valid_mesh(&meshes[i]) || meshes[i].dim != meshes[0].dim) return false;
+    if (params->eq == SHW_BURGERS && meshes[0].dim != 1) return false;
+    if (params->weights == SHW_W_LEARNED && (params->eq != SHW_EULER || meshes[0].dim != 1))
+        return false;
+    return true;
+}
+
 size_t shw_workspace_bytes(const shw_mesh *meshes, int n_inst, const shw_params *params)
 {
-    if (!meshes || n_inst < 1 || !valid_params(params)) return 0;
-    for (int i = 0; i < n_inst; ++i)
-        if (!valid_mesh(&meshes[i]) || meshes[i].dim != meshes[0].dim) return 0;
+    if (!valid_batch(meshes, n_inst, params)) return 0;
     return make_layout(meshes, n_inst, params).total;
 }
 
@@ -151,13 +164,7 @@ shw_status shw_create(const shw_mesh *meshes, int n_inst, const shw_params *para
 {
     if (!out) return SHW_EINVAL;
     *out = nullptr;
-    if (!meshes || n_inst < 1 || !valid_params(params) || !d_state || !d_workspace)
-        return SHW_EINVAL;
-    for (int i = 0; i < n_inst; ++i)
-        if (!valid_mesh(&meshes[i]) || meshes[i].dim != meshes[0].dim) return SHW_EINVAL;
-    if (params->eq == SHW_BURGERS && meshes[0].dim != 1) return SHW_EINVAL;
-    if (params->weights == SHW_W_LEARNED && (params->eq != SHW_EULER || meshes[0].dim != 1))
-        return SHW_EINVAL;
+    if (!valid_batch(meshes, n_inst, params) || !d_state || !d_workspace) return SHW_EINVAL;
     shw_ctx *c = new (std::nothrow) shw_ctx;
     if (!c) return SHW_ENOMEM;
     c->n_inst = n_inst;
@@ -418,6 +425,7 @@ static Loop1D loop_args(shw_ctx *c)
     L.gate = c->at<GateLane>(c->lay.gate);
     const double th = c->params.gate_threshold;
     L.gate_logit_min = (th > 0.0 && th < 1.0) ? (float)std::log(th / (1.0 - th)) : 0.0f;
+    L.gate_every = c->params.gate_every > 0 ? c->params.gate_every : 1;
     return L;
 }
 

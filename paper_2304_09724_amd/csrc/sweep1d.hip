@@ -50,12 +50,22 @@ __device__ __forceinline__ double wave_max(double v)
 
 // One sweep of one instance: src -> dst with step dt; returns true if a new
 // cell average of this thread is non-physical.
+// cell whose gate decision stands for index q (outside the mesh: the
+// periodic image, else the nearest end cell, which covers the mirror images
+// of a reflective end within the same window)
+__device__ __forceinline__ int flag_cell(int q, int n, int bc_lo, int bc_hi)
+{
+    if (q < 0) return bc_lo == BC_PERIODIC ? ((q % n) + n) % n : 0;
+    if (q >= n) return bc_hi == BC_PERIODIC ? q % n : n - 1;
+    return q;
+}
+
 template <int EQ>
 __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__restrict__ src,
                                                double *__restrict__ dst, double dt,
                                                const DevParams &P,
-                                               const uint8_t *__restrict__ flags,
-                                               const u32x4 *gate, float gate_logit_min)
+                                               uint8_t *__restrict__ flags, const u32x4 *gate,
+                                               float gate_logit_min, int gate_since)
 {
     constexpr int M = NComp<EQ, 1>::M;
     const int lane = threadIdx.x % WAVE;
@@ -77,10 +87,25 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
         if (P.weights == W_GATED) full = flags[d.cell_off + s0] != 0;
         if constexpr (EQ == EULER) {
             if (P.weights == W_LEARNED) {
-                // the whole wave evaluates the network for its 64 cells
-                float f[GATE_NF];
-                gate_features1d(Wm, W0, Wp, Vm, Vp, d.dx, P.gamma, f);
-                full = gate_wave_logit(f, gate_lane_lds(gate, lane)) >= gate_logit_min;
+                if (gate_since == 0) {
+                    // the whole wave evaluates the network for its 64 cells;
+                    // the owners keep the decision for the steps until the next
+                    float f[GATE_NF];
+                    gate_features1d(Wm, W0, Wp, Vm, Vp, d.dx, P.gamma, f);
+                    full = gate_wave_logit(f, gate_lane_lds(gate, lane)) >= gate_logit_min;
+                    if (lane >= 1 && lane <= CHUNK && j >= 0 && j < n)
+                        flags[d.cell_off + j] = (uint8_t)full;
+                } else {
+                    // s steps after the gate ran, a cell can need the nonlinear
+                    // weights only if a cell flagged then lies within 2s cells:
+                    // its reconstruction reads its neighbours, and each step
+                    // updates a cell from the reconstructions next to it
+                    const int reach = 2 * gate_since;
+                    unsigned any = 0;
+                    for (int o = -reach; o <= reach; ++o)
+                        any |= flags[d.cell_off + flag_cell(jl + o, n, d.bc_lo, d.bc_hi)];
+                    full = any != 0;
+                }
             }
         }
         double lo[5][M], hi[5][M];
@@ -151,6 +176,7 @@ __global__ void __launch_bounds__(BLOCK) loop1d_kernel(Loop1D Lp, DevParams P)
         const double dt_fix = Lp.dt_fixed ? Lp.dt_fixed[i] : 0.0;
         long long k = 0;
         int code = 0;
+        int gate_since = 0;
         while (k < Lp.max_steps) {
             double dt;
             bool last = false;
@@ -177,7 +203,12 @@ __global__ void __launch_bounds__(BLOCK) loop1d_kernel(Loop1D Lp, DevParams P)
                 dt = P.cfl * d.dx / smax;
                 if (dt >= T - st.t) { dt = T - st.t; last = true; }
             }
-            const bool bad = sweep_instance<EQ>(d, A, B, dt, P, Lp.flags, s_gate, Lp.gate_logit_min);
+            // the gate runs at the first step of a launch and every gate_every
+            // steps of the instance; steps are separated by block barriers, so
+            // the decisions one wave stores are seen by the other waves
+            gate_since = (k == 0 || (st.steps + k) % Lp.gate_every == 0) ? 0 : gate_since + 1;
+            const bool bad = sweep_instance<EQ>(d, A, B, dt, P, Lp.flags, s_gate, Lp.gate_logit_min,
+                                                gate_since);
             const int any_bad = __syncthreads_or(bad);
             double *tmp = A; A = B; B = tmp;
             ++k;

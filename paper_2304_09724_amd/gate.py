@@ -31,9 +31,9 @@ def init_params(seed: int = 0) -> np.ndarray:
 
 
 def collect(problems, times, level=LABEL_LEVEL, device="cuda"):
-    """Features and labels (at the given level) of every cell of a 1D Euler
-    batch, sampled at the given times of plain runs.  problems: list of
-    (mesh, state)."""
+    """Features and labels (the cell's weight test at the given level) of
+    every cell of a 1D Euler batch, sampled at the given times of plain runs.
+    problems: list of (mesh, state)."""
     import torch
     meshes = [m for m, _ in problems]
     s = Solver(meshes, Params.make(eq=EULER, weights=W_NONLINEAR), device=device)

@@ -122,12 +122,13 @@ def test_features_and_labels_match_oracle(level):
     assert off == f.shape[0]
 
 
+@pytest.mark.parametrize("every", [1, 4])
 @pytest.mark.parametrize("b3,mode", [(40.0, S.W_NONLINEAR), (-40.0, S.W_LINEAR)])
-def test_learned_gate_limits(b3, mode):
+def test_learned_gate_limits(b3, mode, every):
     """A gate that calls every cell troubled gives the plain method bit for
     bit (on a Riemann problem); one that calls every cell smooth gives the
     linear-weight scheme (on the smooth density wave, which linear weights
-    can run)."""
+    can run); also with decisions held over several steps."""
     p = np.zeros(S.GATE_NPARAMS, dtype=np.float32)
     p[OB3] = b3
     if b3 > 0:
@@ -137,7 +138,8 @@ def test_learned_gate_limits(b3, mode):
     else:
         m = [S.Mesh.line(64, 0.0, 2.0, S.BC_PERIODIC)]
         st = WL.density_wave_1d(64)
-    a = S.Solver(m, S.Params.make(eq=S.EULER, weights=S.W_LEARNED, gate_threshold=0.5))
+    a = S.Solver(m, S.Params.make(eq=S.EULER, weights=S.W_LEARNED, gate_threshold=0.5,
+                                  gate_every=every))
     a.gate_load(p)
     a.set_state(0, st)
     a.advance_to(0.05, max_steps=20)
@@ -170,16 +172,24 @@ def envelope_excess(rg, rp):
     return float(max((mid - hi).max(), (lo - mid).max(), 0.0))
 
 
-def test_trained_gate_keeps_the_error_of_the_plain_method():
+@pytest.fixture(scope="module")
+def trained():
     X, y = GT.collect(GT.training_problems(), times=[0.0, 0.02, 0.06, 0.1, 0.14])
-    assert 0.01 < float(y.mean()) < 0.5
     params, hist = GT.train(X, y)
+    return X, y, params, hist
+
+
+@pytest.mark.parametrize("every", [1, 3])
+def test_trained_gate_keeps_the_error_of_the_plain_method(trained, every):
+    X, y, params, hist = trained
+    assert 0.01 < float(y.mean()) < 0.5
     assert hist[-1] < 0.5 * hist[0]
     # held-out problems from the batched workload's distribution
     val = WL.riemann_batch_1d(count=12, seed=1234, nmin=100, nmax=400)
     meshes = [S.Mesh.line(d.n, d.x0, d.x1, S.BC_TRANSMISSIVE) for d in val]
     plain = S.Solver(meshes, S.Params.make(eq=S.EULER))
-    gated = S.Solver(meshes, S.Params.make(eq=S.EULER, weights=S.W_LEARNED, gate_threshold=0.05))
+    gated = S.Solver(meshes, S.Params.make(eq=S.EULER, weights=S.W_LEARNED, gate_threshold=0.05,
+                                           gate_every=every))
     gated.gate_load(params)
     for i, d in enumerate(val):
         plain.set_state(i, d.state())
