@@ -40,6 +40,35 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# HBM bytes of one launch of the persistent kernel on this workload, from the
+# two counter runs summarised in profiles/ (FETCH_SIZE and WRITE_SIZE scaled by
+# a 1 GiB copy); valid only for the kernel sources those runs measured.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "loop1d_euler_riemann4096_hbm_counters.md")
+KERNEL_SOURCES = ["sweep1d.hip", "shw_kernels.h", "sweep1d_math.h", "shw_math.h", "gate_math.h"]
+
+
+def kernel_fingerprint():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2304_09724_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """Counted HBM bytes per launch, or None if the kernel changed since."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in text.splitlines()
+                  if line.startswith(("kernel_sources_sha256_16:", "hbm_bytes_per_launch:")))
+    if fields.get("kernel_sources_sha256_16", "").strip() != kernel_fingerprint():
+        return None
+    return float(fields["hbm_bytes_per_launch"])
+
+
 def flops_per_cell_update():
     global FLOPS_PER_CELL_UPDATE
     if FLOPS_PER_CELL_UPDATE is None:
@@ -157,6 +186,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gate", action="store_true")
+    ap.add_argument("--copy-check", type=int, default=0, metavar="BYTES",
+                    help="after the timed steps, copy a device buffer of this many bytes once "
+                         "(a plain copy kernel of known traffic, to scale HBM counters by)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the batch would be "
@@ -213,7 +245,8 @@ def main():
     algo_bytes = 2 * 2 * 3 * 8           # read + write of W and V (3 components) per cell-update
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3),
                 "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved_tflops / FP64_VECTOR_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved_tflops / FP64_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(), "traffic_unit": "bytes per launch (HBM, counted)",
                 "kernel": "loop1d_kernel<EULER> (persistent batched time loop)",
                 "kernel_ms": round(kernel_ms, 3), "flops_per_cell_update": flops,
                 "hbm_algorithmic_GBs": round(algo_bytes * cu_step / (kernel_ms * 1e-3) / 1e9, 1),
@@ -234,6 +267,13 @@ def main():
                                           "updates actually performed are counted",
                       "parallelism": "single GPU, one persistent launch"},
            "roofline": roofline}
+    if args.copy_check > 0:
+        src = torch.ones(args.copy_check // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_check_bytes"] = int(src.numel() * 8)
+        del src, dst
     if not args.no_gate:
         out["gated"] = gated_leg(S, insts, states, meshes, init, args, value, solver)
     if not args.no_cpu_baseline:
