@@ -176,7 +176,50 @@ def gated_leg(S, insts, states, meshes, init, args, plain_value, plain):
             "nonphysical_instances": int((~okg).sum()),
             "smooth_fraction_training_cells": smooth,
             "training": {"samples": int(X.shape[0]), "adam_steps": 800,
-                         "loss_first_last": [hist[0], hist[-1]], "seconds": round(train_s, 2)}}
+                         "loss_first_last": [hist[0], hist[-1]], "seconds": round(train_s, 2)},
+            "gated_2d": gated_2d_leg(S, params)}
+
+
+def gated_2d_leg(S, params, threshold=0.05, steps=40):
+    """The learned gate on 2D Euler: the shock/sine problem (Mach-3 shock into
+    rho = 1 + 0.2 sin 5x sin 3y on (-5,5) x (0,2pi/3); 2048 x 512 cells, a
+    quarter of the 4096 x 1024 shape, whose exact initial averages take
+    minutes on the host), a window of `steps` CFL steps from t = 0, plain and
+    gated: throughput and the gated density's departure from the plain one."""
+    import torch
+    from paper_2304_09724_amd import workloads as WL
+    nx, ny = 2048, 512
+    m = [S.Mesh.rect(nx, ny, -5.0, 5.0, 0.0, 2 * np.pi / 3, S.BC_TRANSMISSIVE, S.BC_PERIODIC)]
+    st = WL.shock_sine_2d(nx, ny)
+    out = {"workload": f"2D Euler shock/sine {nx}x{ny}, {steps} CFL steps from t=0",
+           "unit": "cell-updates/s"}
+    res = {}
+    for name, prm in (("plain", S.Params.make(eq=S.EULER)),
+                      ("gated", S.Params.make(eq=S.EULER, weights=S.W_LEARNED,
+                                              gate_threshold=threshold))):
+        s = S.Solver(m, prm, device="cuda:0")
+        if name == "gated":
+            s.gate_load(params)
+        s.set_state(0, st)
+        init = s.state.clone()
+        s.advance_to(1e9, max_steps=2)
+        s.state.copy_(init)
+        s.set_times(0.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        k = s.advance_to(1e9, max_steps=steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = nx * ny * int(k[0]) / el
+        res[name] = s.get_state(0)[0, 0]
+        if name == "gated":
+            out["cells_gated_nonlinear_last_step"] = float(s.get_flags(0).mean())
+        del s
+    out["speedup"] = out["gated"] / out["plain"]
+    R = float(res["plain"].max() - res["plain"].min())
+    out["max_abs_density_diff_over_range"] = float(np.abs(res["gated"] - res["plain"]).max() / R)
+    out["l1_density_diff"] = float(np.abs(res["gated"] - res["plain"]).mean())
+    return out
 
 
 def main():

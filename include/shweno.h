@@ -77,14 +77,18 @@ typedef struct {
  * small ones (sec. 2.3: 0.994, 0.003, 0.003); charwise: Euler only,
  * reconstruct characteristic fields; weights: SHW_W_* — NONLINEAR is the
  * paper's SHWENO (sec. 2.3), LINEAR uses the linear weights everywhere, GATED
- * takes per-cell flags from shw_set_flags, LEARNED (1D Euler) evaluates the
+ * takes per-cell flags from shw_set_flags, LEARNED (Euler) evaluates the
  * learned gate; gate_threshold (0 < t < 1): a cell whose gate score
  * sigmoid(logit) is >= t takes the full nonlinear reconstruction;
- * gate_every (LEARNED, 1..1024): the gate is evaluated at the first step of
- * each call and then every gate_every steps of an instance; s steps after an
- * evaluation a cell takes the nonlinear weights if any cell within 2s of it
- * was flagged then (the distance the data of a reconstruction can travel in
- * s steps).  LEARNED overwrites the per-cell flags of SHW_W_GATED. */
+ * gate_every (LEARNED, 1..1024; 1D): the gate is evaluated at the first step
+ * of each call and then every gate_every steps of an instance; s steps after
+ * an evaluation a cell takes the nonlinear weights if any cell within 2s of
+ * it was flagged then (the distance the data of a reconstruction can travel
+ * in s steps).  In 2D the gate runs at every step.  LEARNED overwrites the
+ * per-cell flags of SHW_W_GATED.  In GATED and LEARNED modes a wave of cells
+ * takes the characteristic path if any of its cells needs the nonlinear
+ * weights; its linear-weight cells then get the big quartic of their
+ * characteristic fields, equal to the componentwise one up to rounding. */
 typedef struct {
     int eq;
     int charwise;
@@ -106,7 +110,7 @@ size_t shw_state_doubles(const shw_mesh *mesh, const shw_params *params);
 
 /* Bytes of device workspace shw_create needs for this batch, 0 if invalid
  * (meshes of different dimensions, Burgers outside 1D, the learned gate
- * outside 1D Euler, or an invalid mesh or parameter set). */
+ * for another equation than Euler, or an invalid mesh or parameter set). */
 size_t shw_workspace_bytes(const shw_mesh *meshes, int n_inst, const shw_params *params);
 
 /* Create a context for n_inst instances (all with the same dim and params).
@@ -157,14 +161,22 @@ shw_status shw_advance_to(shw_ctx *ctx, const double *T, long long max_steps,
  * host memory.  Synchronising. */
 shw_status shw_set_flags(shw_ctx *ctx, int inst, const uint8_t *flags);
 
+/* The per-cell flags of instance inst as the last step used them (GATED:
+ * those set; LEARNED: the gate's decisions, in 1D the stored ones before
+ * the 2s widening) into host memory (nx * ny bytes).  Synchronising. */
+shw_status shw_get_flags(shw_ctx *ctx, int inst, uint8_t *flags);
+
 /* ---- learned troubled-cell gate (an addition to the paper's method) ------
- * A small network (16 -> 32 -> 32 -> 1, ReLU) scores each cell of a 1D Euler
+ * A small network (16 -> 32 -> 32 -> 1, ReLU) scores each cell of an Euler
  * batch from 16 features of the data its reconstruction reads (sec. 2.3):
  * per conservative component the signed shape of the jumps of the averages
  * and of the neighbours' derivative averages, normalised by its size, and
  * that size; and u / (|u| + c).  Cells whose probability of needing the
  * nonlinear weights is below the threshold use the linear weights, the rest
- * the full SHWENO reconstruction.  The network runs in BF16 on the matrix
+ * the full SHWENO reconstruction.  In 2D (sec. 3.2) a cell is scored along x
+ * and along y from its normal components (rho, m_n, E) with the same network
+ * and takes the nonlinear weights in both stages of both sweeps if either
+ * score reaches the threshold.  The network runs in BF16 on the matrix
  * cores with FP32 accumulation; the scheme itself stays FP64.  Parameters:
  * W1[32][16], b1[32], W2[32][32], b2[32], w3[32], b3, as FP32. */
 

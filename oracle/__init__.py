@@ -119,6 +119,9 @@ def lib():
         L.orc_mlp_backward.argtypes = [ctypes.c_int, _D, _D, _D, ctypes.c_double, _D]
         L.orc_mlp_backward.restype = ctypes.c_double
         L.orc_gate_features1d.argtypes = [P, ctypes.c_int, ctypes.c_double, _D, ctypes.c_int, _D]
+        L.orc_gate_features2d.argtypes = [P, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                          ctypes.c_double, _D, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int, _D]
         L.orc_gate_label1d.argtypes = [P, ctypes.c_int, ctypes.c_double, _D, ctypes.c_int,
                                        ctypes.c_double]
         _lib = L
@@ -236,6 +239,22 @@ def gate_features1d(cfg: Config, state, dx):
         f = np.zeros(N_FEATURES)
         lib().orc_gate_features1d(ctypes.byref(c), n, dx, _p(st), j, _p(f))
         out[j] = f
+    return out
+
+
+def gate_features2d(cfg: Config, state, dx, dy, direction):
+    """(ny, nx, 16) features of every cell of a 2D Euler state (4, 4, ny, nx)
+    along x (direction 0) or y (1)."""
+    st = _f64(state)
+    ny, nx = st.shape[-2:]
+    c = cfg.c()
+    out = np.zeros((ny, nx, N_FEATURES))
+    f = np.zeros(N_FEATURES)
+    for j in range(ny):
+        for i in range(nx):
+            lib().orc_gate_features2d(ctypes.byref(c), nx, ny, dx, dy, _p(st), i, j, direction,
+                                      _p(f))
+            out[j, i] = f
     return out
 
 

@@ -18,6 +18,13 @@
  * and f[15] = u / (|u| + c) at cell j (0 if |u| + c = 0), which sets the
  * characteristic projection.
  *
+ * 2D Euler (sec. 3.2): a cell has such a set along x and along y, each from
+ * the line of cells through it in that direction, with the components
+ * (rho, m_n, E) (m_n the momentum normal to the faces the direction's
+ * sweep crosses), the derivative averages in that direction, and u_n with c
+ * from the full 2D state.  The gate scores both with the same network and
+ * takes the nonlinear weights if either score reaches the threshold.
+ *
  * Label of a cell at level L: 1 ("troubled") if the characteristic nonlinear
  * reconstruction of the cell gives the big quartic a weight below L times its
  * linear weight in some field.
@@ -33,6 +40,8 @@
 void orc_euler_eigen(double gamma, int dim, int dir, const double *W,
                      double *lam, double *R, double *L);
 void orc_cell1d(const orc_cfg *cfg, int n, const double *st, int j, double *W, double *V);
+void orc_cell2d(const orc_cfg *cfg, int nx, int ny, const double *st, int i, int j,
+                double Q[4][4]);
 
 #define H 32
 #define NF 16
@@ -56,6 +65,43 @@ void orc_gate_features1d(const orc_cfg *cfg, int n, double dx, const double *st,
     double a2 = cfg->gamma * p / rho;
     double den = fabs(u) + sqrt(a2 > 0.0 ? a2 : 0.0);
     f[15] = den > 0.0 ? u / den : 0.0;
+}
+
+/* the 16 features of one line of three cells: W[l][c], D[l][c] (derivative
+ * averages along the line) for l = -1, 0, +1; comp: the three components
+ * used; ke: |m|^2 of the centre cell (all momenta) */
+static void line_features(double gamma, const double W[3][4], const double D[3][4],
+                          const int comp[3], double h, double ke, double f[NF])
+{
+    for (int k = 0; k < 3; ++k) {
+        int c = comp[k];
+        double d[4] = {W[1][c] - W[0][c], W[2][c] - W[1][c], h * D[0][c], h * D[2][c]};
+        double S = fabs(d[0]) + fabs(d[1]) + fabs(d[2]) + fabs(d[3]);
+        for (int q = 0; q < 4; ++q) f[5 * k + q] = S >= 1e-30 ? d[q] / S : 0.0;
+        f[5 * k + 4] = log2(S * S + 1e-12) / 32.0;
+    }
+    double rho = W[1][0], un = W[1][comp[1]] / rho;
+    double p = (gamma - 1.0) * (W[1][comp[2]] - 0.5 * ke / rho);
+    double a2 = gamma * p / rho;
+    double den = fabs(un) + sqrt(a2 > 0.0 ? a2 : 0.0);
+    f[15] = den > 0.0 ? un / den : 0.0;
+}
+
+/* features of cell (i, j) of a 2D Euler state along direction dir (0: x, 1: y) */
+void orc_gate_features2d(const orc_cfg *cfg, int nx, int ny, double dx, double dy,
+                         const double *st, int i, int j, int dir, double f[NF])
+{
+    double Q[3][4][4], W[3][4], D[3][4];
+    for (int l = 0; l < 3; ++l) {
+        orc_cell2d(cfg, nx, ny, st, dir == 0 ? i - 1 + l : i, dir == 0 ? j : j - 1 + l, Q[l]);
+        for (int c = 0; c < 4; ++c) {
+            W[l][c] = Q[l][0][c];
+            D[l][c] = Q[l][dir == 0 ? 1 : 2][c];
+        }
+    }
+    const int comp[3] = {0, dir == 0 ? 1 : 2, 3};
+    double ke = W[1][1] * W[1][1] + W[1][2] * W[1][2];
+    line_features(cfg->gamma, W, D, comp, dir == 0 ? dx : dy, ke, f);
 }
 
 /* 1 if a characteristic field's big-stencil weight falls below level times

@@ -127,6 +127,10 @@ int orc_advance2d(const orc_cfg *cfg, int nx, int ny, double dx, double dy,
  * conditions) */
 void orc_gate_features1d(const orc_cfg *cfg, int n, double dx, const double *st, int j,
                          double f[16]);
+/* 16 features of cell (i, j) of a 2D Euler state along dir (0: x, 1: y):
+ * the 1D set on the line through the cell, components (rho, m_n, E) */
+void orc_gate_features2d(const orc_cfg *cfg, int nx, int ny, double dx, double dy,
+                         const double *st, int i, int j, int dir, double f[16]);
 /* 1 if the nonlinear weights of cell j (-1..n: ghosts by the boundary
  * conditions) leave the big stencil below level times its linear weight in
  * some characteristic field */

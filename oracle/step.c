@@ -266,9 +266,10 @@ int orc_advance1d(const orc_cfg *cfg, int n, double dx, double cfl, double T,
 /* 2D                                                                        */
 /* ------------------------------------------------------------------------- */
 
-/* the four averages (W, V, Y, Z; m components each) of cell (i, j) */
-static void cell2d(const orc_cfg *cfg, int nx, int ny, const double *st,
-                   int i, int j, double Q[4][4])
+/* the four averages (W, V, Y, Z; m components each) of cell (i, j), ghosts by
+ * the boundary conditions (also used by the gate's features) */
+void orc_cell2d(const orc_cfg *cfg, int nx, int ny, const double *st, int i, int j,
+                double Q[4][4])
 {
     int m = orc_ncomp(cfg->eq, 2);
     int bx = i < 0 ? cfg->bc[0] : cfg->bc[1];
@@ -373,7 +374,7 @@ static void stage1(const orc_cfg *cfg, int nx, int ny, double dy,
 {
     int m = orc_ncomp(cfg->eq, 2);
     double Q[3][4][4];
-    for (int l = 0; l < 3; ++l) cell2d(cfg, nx, ny, st, i, j - 1 + l, Q[l]);
+    for (int l = 0; l < 3; ++l) orc_cell2d(cfg, nx, ny, st, i, j - 1 + l, Q[l]);
     double a[2][3][4], b[2][2][4], P[2][4][5];
     for (int c = 0; c < m; ++c) {
         for (int l = 0; l < 3; ++l) {
@@ -402,7 +403,7 @@ static void stage2(const orc_cfg *cfg, int nx, int ny, double dx,
 {
     int m = orc_ncomp(cfg->eq, 2);
     double Q[4][4];
-    cell2d(cfg, nx, ny, st, i, j, Q);
+    orc_cell2d(cfg, nx, ny, st, i, j, Q);
     int full = flag2d(cfg, nx, ny, flags, i, j);
     memset(out, 0, sizeof *out);
     for (int g = 0; g < 4; ++g) {

@@ -101,6 +101,7 @@ def lib():
         L.shw_mlp_grad.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_float, vp, vp, vp]
         L.shw_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, vp]
         L.shw_set_flags.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8)]
+        L.shw_get_flags.argtypes = [vp, ctypes.c_int, vp]
         L.shw_status_detail.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_char_p,
                                         ctypes.c_size_t]
         _lib = L
@@ -281,6 +282,14 @@ class Solver:
         lab = torch.empty(cells, dtype=torch.uint8, device=self.device)
         self._check(lib().shw_gate_data(self.ctx, float(level), _vp(f), _vp(lab)))
         return f, lab
+
+    def get_flags(self, i):
+        """Per-cell flags of instance i as the last step used them ((ny, nx)
+        or (nx,) uint8)."""
+        m = self.meshes[i]
+        out = np.zeros(m.nx * m.ny, dtype=np.uint8)
+        self._check(lib().shw_get_flags(self.ctx, i, out.ctypes.data_as(ctypes.c_void_p)))
+        return out.reshape((m.ny, m.nx) if m.dim == 2 else (m.nx,))
 
     def set_flags(self, i, flags):
         f = np.ascontiguousarray(np.asarray(flags, dtype=np.uint8).reshape(-1))

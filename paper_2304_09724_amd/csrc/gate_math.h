@@ -84,36 +84,55 @@ __device__ __forceinline__ bf16x8 to_bf16(const float *x)
     return __builtin_convertvector(v, bf16x8);      // round to nearest even
 }
 
-// Features of one 1D Euler cell from exactly the data its reconstruction
-// reads (sec. 2.3: averages of cells j-1, j, j+1 and derivative averages of
-// cells j-1, j+1).  Per conservative component c, with dl, dr the jumps of the
-// averages, gm, gp the neighbours' derivative averages times dx and
-// S = |dl| + |dr| + |gm| + |gp|: the signed shape (dl, dr, gm, gp) / S (zero
-// if S < 1e-30) and log2(S^2 + 1e-12) / 32 (the size against the weights'
-// regulariser); then u / (|u| + c) of the cell, which sets the characteristic
-// projection.  The differences are formed in FP64, the rest in FP32.
-__device__ __forceinline__ void gate_features1d(const double Wm[3], const double W0[3],
-                                                const double Wp[3], const double Vm[3],
-                                                const double Vp[3], double dx, double gamma,
-                                                float f[GATE_NF])
+// Features of one Euler cell along one direction, from exactly the data its
+// reconstruction in that direction reads (sec. 2.3; in 2D, sec. 3.2, the
+// averages of the line's cells j-1, j, j+1 and the derivative averages of
+// j-1, j+1).  Arrays hold the conservative components in the direction's
+// frame: M = 3 (rho, m, E) in 1D, M = 4 (rho, m_n, m_t, E) in 2D; the tangential
+// momentum, which the 1D network never saw, is left out.  Per component c of
+// (rho, m_n, E), with dl, dr the jumps of the averages, gm, gp the
+// neighbours' derivative averages times dx and S = |dl| + |dr| + |gm| + |gp|:
+// the signed shape (dl, dr, gm, gp) / S (zero if S < 1e-30) and
+// log2(S^2 + 1e-12) / 32 (the size against the weights' regulariser); then
+// u_n / (|u_n| + c) of the cell, which sets the characteristic projection.
+// The differences are formed in FP64, the rest in FP32.
+template <int M>
+__device__ __forceinline__ void gate_features(const double Wm[M], const double W0[M],
+                                              const double Wp[M], const double Vm[M],
+                                              const double Vp[M], double dx, double gamma,
+                                              float f[GATE_NF])
 {
+    static_assert(M == 3 || M == 4, "Euler in 1D or 2D");
+    const int comp[3] = {0, 1, M - 1};
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
+    for (int k3 = 0; k3 < 3; ++k3) {
+        const int c = comp[k3];
         const float d[4] = {(float)(W0[c] - Wm[c]), (float)(Wp[c] - W0[c]), (float)(dx * Vm[c]),
                             (float)(dx * Vp[c])};
         const float S = fabsf(d[0]) + fabsf(d[1]) + fabsf(d[2]) + fabsf(d[3]);
         const float iS = S >= 1e-30f ? __builtin_amdgcn_rcpf(S) : 0.0f;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) f[5 * c + k] = d[k] * iS;
-        f[5 * c + 4] = log2f(S * S + 1e-12f) * (1.0f / 32.0f);
+        for (int k = 0; k < 4; ++k) f[5 * k3 + k] = d[k] * iS;
+        f[5 * k3 + 4] = log2f(S * S + 1e-12f) * (1.0f / 32.0f);
     }
-    const float rho = (float)W0[0], m = (float)W0[1], E = (float)W0[2];
+    const float rho = (float)W0[0], E = (float)W0[M - 1];
     const float irho = __builtin_amdgcn_rcpf(rho);
-    const float u = m * irho;
-    const float p = (float)(gamma - 1.0) * (E - 0.5f * m * u);
+    float ke = 0.0f;
+#pragma unroll
+    for (int c = 1; c < M - 1; ++c) ke += (float)W0[c] * (float)W0[c];
+    const float u = (float)W0[1] * irho;
+    const float p = (float)(gamma - 1.0) * (E - 0.5f * ke * irho);
     const float a2 = (float)gamma * p * irho;
     const float den = fabsf(u) + sqrtf(fmaxf(a2, 0.0f));
     f[15] = den > 0.0f ? u * __builtin_amdgcn_rcpf(den) : 0.0f;
+}
+
+__device__ __forceinline__ void gate_features1d(const double Wm[3], const double W0[3],
+                                                const double Wp[3], const double Vm[3],
+                                                const double Vp[3], double dx, double gamma,
+                                                float f[GATE_NF])
+{
+    gate_features<3>(Wm, W0, Wp, Vm, Vp, dx, gamma, f);
 }
 
 // Training label of one 1D Euler cell at level L: 1 if, in the cell's

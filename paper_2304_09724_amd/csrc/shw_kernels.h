@@ -73,7 +73,10 @@ struct Step2D {
     int *bad;                  // per instance sticky non-physical flag
     int *active;               // instances still running after the last step
     InstState *ist;
-    const uint8_t *flags;      // per cell gate flags (GATED mode)
+    uint8_t *flags;            // per cell gate flags (read in GATED mode; in LEARNED
+                               // mode written by the gate kernel at each step)
+    const GateLane *gate;      // packed network (LEARNED mode)
+    float gate_logit_min;      // cells with logit >= this take the full reconstruction
 };
 
 int sweep2d_tiles(int n_sweep, int n_trans);

@@ -141,15 +141,14 @@ size_t shw_state_doubles(const shw_mesh *mesh, const shw_params *params)
 }
 
 // a batch: valid meshes of one dimension, and an equation / weight mode the
-// library runs in that dimension
+// library runs in that dimension (Burgers 1D only, the learned gate Euler only)
 static bool valid_batch(const shw_mesh *meshes, int n_inst, const shw_params *params)
 {
     if (!meshes || n_inst < 1 || !valid_params(params)) return false;
     for (int i = 0; i < n_inst; ++i)
         if (!valid_mesh(&meshes[i]) || meshes[i].dim != meshes[0].dim) return false;
     if (params->eq == SHW_BURGERS && meshes[0].dim != 1) return false;
-    if (params->weights == SHW_W_LEARNED && (params->eq != SHW_EULER || meshes[0].dim != 1))
-        return false;
+    if (params->weights == SHW_W_LEARNED && params->eq != SHW_EULER) return false;
     return true;
 }
 
@@ -408,6 +407,9 @@ static Step2D step2d_args(shw_ctx *c)
     S.active = c->at<int>(c->lay.active);
     S.ist = c->ist();
     S.flags = c->at<uint8_t>(c->lay.flags);
+    S.gate = c->at<GateLane>(c->lay.gate);
+    const double th = c->params.gate_threshold;
+    S.gate_logit_min = (th > 0.0 && th < 1.0) ? (float)std::log(th / (1.0 - th)) : 0.0f;
     return S;
 }
 
@@ -535,6 +537,16 @@ shw_status shw_set_flags(shw_ctx *c, int inst, const uint8_t *flags)
                                          hipMemcpyHostToDevice, c->stream), "set_flags");
     if (s != SHW_OK) return s;
     return c->hip(hipStreamSynchronize(c->stream), "set_flags sync");
+}
+
+shw_status shw_get_flags(shw_ctx *c, int inst, uint8_t *flags)
+{
+    if (!c || !flags || inst < 0 || inst >= c->n_inst) return SHW_EINVAL;
+    const size_t n = (size_t)c->meshes[inst].nx * c->meshes[inst].ny;
+    shw_status s = c->hip(hipMemcpyAsync(flags, c->ws + c->lay.flags + c->cell_off[inst], n,
+                                         hipMemcpyDeviceToHost, c->stream), "get_flags");
+    if (s != SHW_OK) return s;
+    return c->hip(hipStreamSynchronize(c->stream), "get_flags sync");
 }
 
 static unsigned short host_bf16(float f)

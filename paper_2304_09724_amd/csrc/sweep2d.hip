@@ -127,18 +127,24 @@ __global__ void __launch_bounds__(BLOCK) sweep2d_kernel(Step2D S, DevParams P)
     __shared__ double s_poly[2][M][5][BLOCK];
     double Wc[M];
     bool full = P.weights == W_NONLINEAR;
+    bool charpath;
     {
         double PW[M][5], PV[M][5];
+        double W[3][M], V[3][M], Y[3][M], Z[3][M];
         if (live) {
-            double W[3][M], V[3][M], Y[3][M], Z[3][M];
             long long o = 0;
 #pragma unroll
             for (int l = 0; l < 3; ++l) {
                 const long long ol = load_cell2d<EQ, M, DIR>(src, d, s, t - 1 + l, W[l], V[l], Y[l], Z[l]);
                 if (l == 1) o = ol;
             }
-            if (P.weights == W_GATED) full = S.flags[d.cell_off + o] != 0;
-            stage1<M, EQ>(W, V, Y, Z, dT, full, P, PW, PV);
+            if (P.weights == W_GATED || P.weights == W_LEARNED) full = S.flags[d.cell_off + o] != 0;
+        }
+        // one reconstruction path per wave: characteristic if any lane needs
+        // the nonlinear weights
+        charpath = __any(full);
+        if (live) {
+            stage1<M, EQ>(W, V, Y, Z, dT, full, charpath, P, PW, PV);
 #pragma unroll
             for (int c = 0; c < M; ++c) Wc[c] = W[1][c];
         } else {
@@ -171,10 +177,13 @@ __global__ void __launch_bounds__(BLOCK) sweep2d_kernel(Step2D S, DevParams P)
 #pragma unroll 1
     for (int g = 0; g < 4; ++g) {
         // characteristic fields of the sweep Jacobian at the cell average
+        // (read by stage 2 on characteristic waves only)
         double Lm[M][M], Rm[M][M];
         if constexpr (EQ == EULER) {
-            double lam[M];
-            euler_eigen<2, 0>(Wc, P.gamma, Rm, Lm, lam);
+            if (charpath && P.charwise) {
+                double lam[M];
+                euler_eigen<2, 0>(Wc, P.gamma, Rm, Lm, lam);
+            }
         } else {
             Lm[0][0] = 1.0; Rm[0][0] = 1.0;
         }
@@ -207,7 +216,8 @@ __global__ void __launch_bounds__(BLOCK) sweep2d_kernel(Step2D S, DevParams P)
             }
             double lo[5][M], hi[5][M];
             if (lane >= 1 && lane <= 62 && live) {
-                stage2_order<M, EQ>(n, am, a0, ap, bm, bp, Lm, Rm, dS, scs, full, P, w, lo, hi);
+                stage2_order<M, EQ>(n, am, a0, ap, bm, bp, Lm, Rm, dS, scs, full, charpath, P, w,
+                                    lo, hi);
             } else {
 #pragma unroll
                 for (int a = 0; a < 5; ++a)
@@ -307,6 +317,55 @@ __global__ void __launch_bounds__(BLOCK) sweep2d_kernel(Step2D S, DevParams P)
 }
 
 // max over the cells of (|u|+c)/dx + (|v|+c)/dy, one block per instance
+// The learned gate of one 2D Euler step: for every cell of the instances
+// that step, the network scores the cell along x and along y (features of the
+// line through the cell in that direction, its normal components; the
+// network is the 1D one) and the cell takes the nonlinear weights if either
+// score reaches the threshold.  Both sweeps of the step read the flags.
+// Tiles as for the x-sweep: 4 rows x 60 cells, one wave per row, lane l on
+// cell c0 + l - 2 (every lane evaluates; lanes 2..61 store).
+__global__ void __launch_bounds__(BLOCK) gate2d_kernel(Step2D S, DevParams P)
+{
+    constexpr int M = 4;
+    __shared__ u32x4 s_gate[GATE_LDS_WORDS];
+    const int inst = find_instance(S.tile_off[0], S.n_inst, blockIdx.x);
+    if (!(S.dt[inst] > 0.0)) return;              // the whole block: instance idle
+    gate_to_lds(S.gate, s_gate, threadIdx.x, BLOCK);
+    __syncthreads();
+    const Inst2D d = S.inst[inst];
+    const int tiles_s = (d.nx + CHUNK - 1) / CHUNK;
+    const int tile = blockIdx.x - S.tile_off[0][inst];
+    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+    const int t = (tile / tiles_s) * LINES + wave;
+    if (t >= d.ny) return;                        // the whole wave: past the last row
+    const int s = (tile % tiles_s) * CHUNK + lane - 2;
+    const int sc = s < 0 ? 0 : (s >= d.nx ? d.nx - 1 : s);   // lanes off the row: any cell
+    const double *src = (S.parity[inst] ? S.alt : S.state) + d.off;
+    const GateLane G = gate_lane_lds(s_gate, lane);
+    float z[2];
+    {
+        double Wm[M], W0[M], Wp[M], Vm[M], V0[M], Vp[M], Y[M], Z[M];
+        load_cell2d<EULER, M, 0>(src, d, sc - 1, t, Wm, Vm, Y, Z);
+        load_cell2d<EULER, M, 0>(src, d, sc, t, W0, V0, Y, Z);
+        load_cell2d<EULER, M, 0>(src, d, sc + 1, t, Wp, Vp, Y, Z);
+        float f[GATE_NF];
+        gate_features<M>(Wm, W0, Wp, Vm, Vp, d.dx, P.gamma, f);
+        z[0] = gate_wave_logit(f, G);
+    }
+    {
+        double Wm[M], W0[M], Wp[M], Vm[M], V0[M], Vp[M], Y[M], Z[M];
+        load_cell2d<EULER, M, 1>(src, d, t - 1, sc, Wm, Vm, Y, Z);
+        load_cell2d<EULER, M, 1>(src, d, t, sc, W0, V0, Y, Z);
+        load_cell2d<EULER, M, 1>(src, d, t + 1, sc, Wp, Vp, Y, Z);
+        float f[GATE_NF];
+        gate_features<M>(Wm, W0, Wp, Vm, Vp, d.dy, P.gamma, f);
+        z[1] = gate_wave_logit(f, G);
+    }
+    if (lane >= 2 && lane <= 61 && s < d.nx)
+        S.flags[d.cell_off + (long long)t * d.nx + s] =
+            (uint8_t)(fmaxf(z[0], z[1]) >= S.gate_logit_min);
+}
+
 template <int EQ>
 __global__ void __launch_bounds__(BLOCK) speed2d_kernel(Step2D S, DevParams P, int use_parity)
 {
@@ -430,6 +489,8 @@ hipError_t launch_step2d(int eq, const Step2D &S, const DevParams &P, int fixed,
 {
     const int nb = (S.n_inst + 255) / 256;
     prepare2d_kernel<<<nb, 256, 0, st>>>(S, P, fixed);
+    if (eq == EULER && P.weights == W_LEARNED)
+        gate2d_kernel<<<total_tiles[0], BLOCK, 0, st>>>(S, P);
     if (eq == EULER) {
         sweep2d_kernel<EULER, 0><<<total_tiles[0], BLOCK, 0, st>>>(S, P);
         sweep2d_kernel<EULER, 1><<<total_tiles[1], BLOCK, 0, st>>>(S, P);

@@ -26,15 +26,19 @@ SHW_HD constexpr int jidx(int a, int n)
 // [2] above).  One weight set (from the {W, Y} data) serves both, as one set
 // of weights serves the function and its derivatives (sec. 2.1.2).  Euler:
 // characteristic fields of the transverse Jacobian at the cell's average.
+// full: nonlinear weights, else the linear ones (the big quartics alone);
+// charpath (a whole wave's choice): work in characteristic fields, which for
+// linear weights gives the componentwise polynomials up to rounding.
 // Output: polynomials in eta = (t - t_j)/dt of the cell's line average of W
 // (PW) and of W_s (PV), per conservative component.
 // --------------------------------------------------------------------------
 template <int M, int EQ, class Re>
 SHW_HD void stage1(const Re W[3][M], const Re V[3][M], const Re Y[3][M], const Re Z[3][M],
-                   double dT, bool full, const DevParams &P, Re PW[M][5], Re PV[M][5])
+                   double dT, bool full, bool charpath, const DevParams &P, Re PW[M][5],
+                   Re PV[M][5])
 {
     if constexpr (EQ == EULER) {
-        if (full && P.charwise) {
+        if (charpath && P.charwise) {
             Re R[M][M], L[M][M], lam[M];
             euler_eigen<2, 1>(W[1], P.gamma, R, L, lam);
             Re cw[M][5], cv[M][5];
@@ -63,12 +67,14 @@ SHW_HD void stage1(const Re W[3][M], const Re V[3][M], const Re Y[3][M], const R
                     bw[l] = dT * sy;
                     bv[l] = dT * sz;
                 }
-                Re w[3];
                 big_quartic(aw[0], aw[1], aw[2], bw[0], bw[1], cw[f]);
-                nonlinear_weights(cw[f], aw[0], aw[1], aw[2], P, w);
-                combine(cw[f], aw[0], aw[1], aw[2], w, P);
                 big_quartic(av[0], av[1], av[2], bv[0], bv[1], cv[f]);
-                combine(cv[f], av[0], av[1], av[2], w, P);
+                if (full) {
+                    Re w[3];
+                    nonlinear_weights(cw[f], aw[0], aw[1], aw[2], P, w);
+                    combine(cw[f], aw[0], aw[1], aw[2], w, P);
+                    combine(cv[f], av[0], av[1], av[2], w, P);
+                }
             }
 #pragma unroll
             for (int c = 0; c < M; ++c)
@@ -131,16 +137,18 @@ SHW_HD Re deriv_at(const Re c[5], double eta, int n, double scale)
 // d^n/dt^n of the line averages of W of cells l = -1, 0, +1 and b[l] = the
 // same for W_s of cells -1, +1 (scaled by ds inside).  Weights come from the
 // order-0 data (w is filled when n == 0 and reused for n >= 1).  Euler:
-// characteristic fields of the sweep Jacobian at the cell's average (L, R).
+// characteristic fields of the sweep Jacobian at the cell's average (L, R),
+// when charpath (a whole wave's choice; L, R are not read otherwise); full
+// selects nonlinear or linear weights as in stage 1.
 // Writes d^{a+n}W/ds^a dt^n at s = -1/2 (lo[a]) and s = +1/2 (hi[a]), a <= 4 - n.
 // --------------------------------------------------------------------------
 template <int M, int EQ, class Re>
 SHW_HD void stage2_order(int n, const Re am[M], const Re a0[M], const Re ap[M], const Re bm[M],
                          const Re bp[M], const Re L[M][M], const Re R[M][M], double dS,
-                         const double scs[5], bool full, const DevParams &P, Re w[M][3],
-                         Re lo[5][M], Re hi[5][M])
+                         const double scs[5], bool full, bool charpath, const DevParams &P,
+                         Re w[M][3], Re lo[5][M], Re hi[5][M])
 {
-    const bool proj = EQ == EULER && full && P.charwise;
+    const bool proj = EQ == EULER && charpath && P.charwise;
     Re clo[M][5], chi[M][5];
 #pragma unroll
     for (int f = 0; f < M; ++f) {

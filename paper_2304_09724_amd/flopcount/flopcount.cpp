@@ -108,7 +108,7 @@ static void euler2d(bool full, const char *name)
     g = Tally();
     for (int dir = 0; dir < 2; ++dir) {
         Cnt PW[M][5], PV[M][5];
-        stage1<M, EULER>(W, V, Y, Z, 0.01, full, P, PW, PV);
+        stage1<M, EULER>(W, V, Y, Z, 0.01, full, full, P, PW, PV);
         for (int gn = 0; gn < 4; ++gn) {
             const double eta = gn == 0 ? -0.5 : gn == 1 ? -LOB_H : gn == 2 ? LOB_H : 0.5;
             Cnt Lm[M][M], Rm[M][M], lam[M];
@@ -121,7 +121,7 @@ static void euler2d(bool full, const char *name)
                     a0[c] = deriv_at(PW[c], eta, n, sc[n]);
                     b0[c] = deriv_at(PV[c], eta, n, sc[n]);
                 }
-                stage2_order<M, EULER>(n, a0, a0, a0, b0, b0, Lm, Rm, 0.01, sc, full, P, w, lo, hi);
+                stage2_order<M, EULER>(n, a0, a0, a0, b0, b0, Lm, Rm, 0.01, sc, full, full, P, w, lo, hi);
                 for (int a = 0; a + n <= 4; ++a)
                     for (int c = 0; c < M; ++c) {
                         JL[jidx(a, n)][c] = hi[a][c];

@@ -51,13 +51,19 @@ def collect(problems, times, level=LABEL_LEVEL, device="cuda"):
 
 
 def training_problems(seed: int = 7, count: int = 48):
-    """Riemann problems (the batched workload's distribution, smaller meshes)
-    and smooth density waves: troubled and smooth cells."""
+    """Riemann problems (the batched workload's distribution, smaller
+    meshes), density waves moving and at rest at several wavenumbers, and the
+    shock/sine problem: troubled and smooth cells of the kinds the gate
+    meets."""
     probs = []
     for d in WL.riemann_batch_1d(count=count, seed=seed, nmin=100, nmax=400):
         probs.append((Mesh.line(d.n, d.x0, d.x1, BC_TRANSMISSIVE), d.state()))
-    for n in (40, 80, 160):
-        probs.append((Mesh.line(n, 0.0, 2.0, BC_PERIODIC), WL.density_wave_1d(n)))
+    for u, amp, k in ((1.0, 0.2, 1), (0.0, 0.2, 1), (0.5, 0.2, 2), (-1.0, 0.1, 3), (0.0, 0.2, 4)):
+        for n in (40, 80, 160):
+            probs.append((Mesh.line(n, 0.0, 2.0, BC_PERIODIC),
+                          WL.density_wave_1d(n, u=u, amp=amp, k=k)))
+    for n in (400, 800):
+        probs.append((Mesh.line(n, -5.0, 5.0, BC_TRANSMISSIVE), WL.shock_sine_1d(n)))
     return probs
 
 

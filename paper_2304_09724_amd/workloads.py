@@ -95,15 +95,42 @@ def burgers_sine(n: int, x0=0.0, x1=2.0):
     return np.ascontiguousarray(np.stack([Wbar[None], V[None]]))
 
 
-def density_wave_1d(n: int, t: float = 0.0, gamma=GAMMA, x0=0.0, x1=2.0):
-    """rho = 1 + 0.2 sin(pi (x - t)), u = p = 1 on periodic (0, 2)
-    (sec. 5, 1D Euler accuracy example).  Exact averages at time t."""
-    e = np.linspace(x0, x1, n + 1) - t
+def density_wave_1d(n: int, t: float = 0.0, gamma=GAMMA, x0=0.0, x1=2.0, u=1.0, amp=0.2,
+                    k=1):
+    """rho = 1 + amp sin(k pi (x - u t)), velocity u, p = 1 on periodic (0, 2)
+    (sec. 5, the 1D Euler accuracy example has u = 1, amp = 0.2, k = 1).
+    Exact averages at time t."""
+    e = np.linspace(x0, x1, n + 1) - u * t
     dx = (x1 - x0) / n
-    rbar = 1.0 - 0.2 * (np.cos(np.pi * e[1:]) - np.cos(np.pi * e[:-1])) / (np.pi * dx)
-    rv = 0.2 * (np.sin(np.pi * e[1:]) - np.sin(np.pi * e[:-1])) / dx
-    Wbar = np.stack([rbar, rbar, 1.0 / (gamma - 1) + 0.5 * rbar])
-    V = np.stack([rv, rv, 0.5 * rv])
+    w = k * np.pi
+    rbar = 1.0 - amp * (np.cos(w * e[1:]) - np.cos(w * e[:-1])) / (w * dx)
+    rv = amp * (np.sin(w * e[1:]) - np.sin(w * e[:-1])) / dx
+    Wbar = np.stack([rbar, u * rbar, 1.0 / (gamma - 1) + 0.5 * u * u * rbar])
+    V = np.stack([rv, u * rv, 0.5 * u * u * rv])
+    return np.ascontiguousarray(np.stack([Wbar, V]))
+
+
+def shock_sine_1d(n: int, gamma=GAMMA):
+    """Mach-3 shock at x = -4 moving right into rho = 1 + 0.2 sin(5x) at rest,
+    p = 1, on (-5, 5) (sec. 5, the Shu-Osher example).  n a multiple of 10
+    puts the shock on a cell edge; each cell's averages come from its own
+    side (derivative averages over the open cell)."""
+    assert n % 10 == 0
+    post = (3.857143, 2.629369, 10.333333)
+    x0, x1 = -5.0, 5.0
+    e = np.linspace(x0, x1, n + 1)
+    dx = (x1 - x0) / n
+
+    def fun(x, left):
+        rho = np.where(left, post[0], 1.0 + 0.2 * np.sin(5 * x))
+        u = np.where(left, post[1], 0.0)
+        p = np.where(left, post[2], 1.0)
+        return prim_to_cons(rho, u, p, gamma=gamma)
+
+    left = (0.5 * (e[:-1] + e[1:]) < -4.0)
+    xq, wq = _gl_nodes(e[:-1], e[1:])
+    Wbar = (np.asarray(fun(xq, left[:, None])) * wq).sum(-1)
+    V = (np.asarray(fun(e[1:], left)) - np.asarray(fun(e[:-1], left))) / dx
     return np.ascontiguousarray(np.stack([Wbar, V]))
 
 
@@ -125,15 +152,27 @@ def riemann_1d(n: int, left, right, x0=0.0, x1=1.0, xd=0.5, gamma=GAMMA):
 # 2D
 # ---------------------------------------------------------------------------
 
-def averages_2d(fun, x0, x1, y0, y1, nx, ny, xbreak=None):
+def averages_2d(fun, x0, x1, y0, y1, nx, ny, xbreak=None, max_points=1 << 24):
     """Exact-quadrature averages (W, V, Y, Z) of fun -> (m, ...) on a uniform
     nx x ny grid.  Without xbreak, fun(x, y) must be smooth.  With xbreak, fun
     may jump across the vertical line x = xbreak and is called as
     fun(x, y, side), side = -1 / +1 selecting the piece left / right of it
-    (so points on the line are unambiguous)."""
-    ex = np.linspace(x0, x1, nx + 1)
+    (so points on the line are unambiguous).  Large grids go by blocks of
+    rows of at most max_points quadrature points."""
     ey = np.linspace(y0, y1, ny + 1)
-    dx, dy = (x1 - x0) / nx, (y1 - y0) / ny
+    rows = max(1, max_points // (nx * len(_GL_W) ** 2))
+    if ny > rows:
+        parts = [_averages_2d_rows(fun, x0, x1, ey[r:min(r + rows, ny) + 1], nx, (y1 - y0) / ny,
+                                   xbreak) for r in range(0, ny, rows)]
+        return np.ascontiguousarray(np.concatenate(parts, axis=-2))
+    return _averages_2d_rows(fun, x0, x1, ey, nx, (y1 - y0) / ny, xbreak)
+
+
+def _averages_2d_rows(fun, x0, x1, ey, nx, dy, xbreak):
+    """averages_2d on the rows between the edges ey."""
+    ex = np.linspace(x0, x1, nx + 1)
+    ny = len(ey) - 1
+    dx = (x1 - x0) / nx
     a, b = ex[:-1], ex[1:]
     if xbreak is None:
         pieces = [(a, b, np.zeros(nx))]

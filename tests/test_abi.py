@@ -62,12 +62,24 @@ def test_invalid_parameters_are_rejected_on_the_host(kw):
     assert state_doubles(line(), S.Params.make(**args)) == 0
 
 
-def test_learned_gate_is_1d_euler_only():
-    p = S.Params.make(eq=S.EULER, weights=S.W_LEARNED, gate_threshold=0.5)
-    assert state_doubles(line(), p) > 0
+def workspace(mesh, params):
+    arr = (S.Mesh * 1)(mesh)
+    return S.lib().shw_workspace_bytes(arr, 1, ctypes.byref(params))
+
+
+def test_learned_gate_is_euler_only():
     rect = S.Mesh.rect(16, 16, 0.0, 1.0, 0.0, 1.0)
-    arr = (S.Mesh * 1)(rect)
-    assert S.lib().shw_workspace_bytes(arr, 1, ctypes.byref(p)) == 0
+    for mesh in (line(), rect):
+        p = S.Params.make(eq=S.EULER, weights=S.W_LEARNED, gate_threshold=0.5)
+        assert workspace(mesh, p) > 0
+        p = S.Params.make(eq=S.ADVECTION, weights=S.W_LEARNED, gate_threshold=0.5)
+        assert workspace(mesh, p) == 0
+
+
+def test_burgers_is_1d_only():
+    rect = S.Mesh.rect(16, 16, 0.0, 1.0, 0.0, 1.0)
+    assert workspace(line(), S.Params.make(eq=S.BURGERS)) > 0
+    assert workspace(rect, S.Params.make(eq=S.BURGERS)) == 0
 
 
 def bf16_bits(x):

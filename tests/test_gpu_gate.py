@@ -227,3 +227,144 @@ def test_trained_gate_keeps_the_error_of_the_plain_method(trained, every):
     # and passes few cells the label calls troubled
     lv = lv.cpu().numpy().astype(bool)
     assert (passed & lv).sum() <= 0.05 * lv.sum()
+
+
+# ---- 2D --------------------------------------------------------------------
+
+QUADS = [(1.5, 0.0, 0.0, 1.5), (0.5323, 1.206, 0.0, 0.3), (0.138, 1.206, 1.206, 0.029),
+         (0.5323, 0.0, 1.206, 0.3)]
+
+
+@pytest.mark.parametrize("b3,mode", [(40.0, S.W_NONLINEAR), (-40.0, S.W_LINEAR)])
+def test_learned_gate_limits_2d(b3, mode):
+    """2D: a gate that calls every cell troubled gives the plain method bit
+    for bit (a four-quadrant problem, ragged against the 60-cell tiles); one
+    that calls every cell smooth gives the linear-weight scheme (the smooth
+    2D density wave)."""
+    p = np.zeros(S.GATE_NPARAMS, dtype=np.float32)
+    p[OB3] = b3
+    if b3 > 0:
+        n = 70
+        m = [S.Mesh.rect(n, n, 0.0, 1.0, 0.0, 1.0, S.BC_TRANSMISSIVE, S.BC_TRANSMISSIVE)]
+        st = WL.four_quadrant(n, QUADS)
+        T = 0.05
+    else:
+        m = [S.Mesh.rect(40, 36, 0.0, 2.0, 0.0, 2.0)]
+        st = WL.density_wave_2d(40, 36)
+        T = 0.1
+    a = S.Solver(m, S.Params.make(eq=S.EULER, weights=S.W_LEARNED, gate_threshold=0.5))
+    a.gate_load(p)
+    a.set_state(0, st)
+    a.advance_to(T, max_steps=30)
+    b = S.Solver(m, S.Params.make(eq=S.EULER, weights=mode))
+    b.set_state(0, st)
+    b.advance_to(T, max_steps=30)
+    assert np.array_equal(a.get_state(0), b.get_state(0))
+
+
+def quads_of(seed, k):
+    return WL.four_quadrant_batch(count=k + 1, seed=seed)[k].quads
+
+
+@pytest.mark.parametrize("bcy", [S.BC_PERIODIC, S.BC_REFLECTIVE])
+def test_2d_gate_decisions_match_the_oracle_network(trained, bcy):
+    """The flags of one 2D step are the FP64 oracle network's decisions on
+    the oracle's features along x and along y (either reaching the
+    threshold), wherever the oracle's logit is not within BF16 reach of the
+    threshold; ragged 70 x 66 mesh, transmissive in x."""
+    params = trained[2]
+    nx, ny = 70, 66
+    st = WL.four_quadrant(70, quads_of(11, 1))[:, :, :ny, :].copy()
+    m = [S.Mesh.rect(nx, ny, 0.0, 1.0, 0.0, ny / 70.0, S.BC_TRANSMISSIVE, bcy)]
+    s = S.Solver(m, S.Params.make(eq=S.EULER, weights=S.W_LEARNED, gate_threshold=0.05))
+    s.gate_load(params)
+    s.set_state(0, st)
+    s.advance_to(0.03)
+    st = s.get_state(0)
+    s.step(s.compute_dt())
+    flags = s.get_flags(0).astype(bool)
+    cfg = O.Config(eq=O.EULER, bc=(O.BC_TRANSMISSIVE, O.BC_TRANSMISSIVE, bcy, bcy))
+    dx, dy = 1.0 / 70, (ny / 70.0) / ny
+    p64 = params.astype(np.float64)
+    z = np.stack([O.mlp_forward(p64, O.gate_features2d(cfg, st, dx, dy, d).reshape(-1, 16))
+                  for d in (0, 1)]).max(axis=0).reshape(ny, nx)
+    zmin = np.log(0.05 / 0.95)
+    clear = np.abs(z - zmin) > 0.5 + 0.05 * np.abs(z)
+    assert clear.mean() > 0.9
+    assert np.array_equal(flags[clear], (z >= zmin)[clear])
+    assert flags.any() and not flags.all()
+
+
+def total_variation_2d(r):
+    return float(np.abs(np.diff(r, axis=0)).sum() + np.abs(np.diff(r, axis=1)).sum())
+
+
+def envelope_excess_2d(rg, rp):
+    """How far the gated density leaves the plain one's 3x3 local min/max."""
+    from numpy.lib.stride_tricks import sliding_window_view as win
+    w = win(rp, (3, 3))
+    lo, hi = w.min(axis=(-1, -2)), w.max(axis=(-1, -2))
+    mid = rg[1:-1, 1:-1]
+    return float(max((mid - hi).max(), (lo - mid).max(), 0.0))
+
+
+@pytest.mark.parametrize("case", ["four_quadrant", "shock_sine"])
+def test_trained_gate_keeps_the_2d_solution(trained, case):
+    """The 1D-trained network gating a 2D run: density within 1e-3 of the
+    plain run's range everywhere, no extra total variation, no overshoot of
+    the plain solution's 3x3 envelope beyond 1e-3 of the range, and most
+    cells passed as smooth."""
+    params = trained[2]
+    if case == "four_quadrant":
+        n = 128
+        m = [S.Mesh.rect(n, n, 0.0, 1.0, 0.0, 1.0, S.BC_TRANSMISSIVE, S.BC_TRANSMISSIVE)]
+        st, T = WL.four_quadrant(n, quads_of(11, 1)), 0.1
+    else:
+        m = [S.Mesh.rect(320, 64, -5.0, 5.0, 0.0, 2 * np.pi / 3, S.BC_TRANSMISSIVE,
+                         S.BC_PERIODIC)]
+        st, T = WL.shock_sine_2d(320, 64), 0.3
+    plain = S.Solver(m, S.Params.make(eq=S.EULER))
+    gated = S.Solver(m, S.Params.make(eq=S.EULER, weights=S.W_LEARNED, gate_threshold=0.05))
+    gated.gate_load(params)
+    for s in (plain, gated):
+        s.set_state(0, st)
+        s.advance_to(T)
+    rp, rg = plain.get_state(0)[0, 0], gated.get_state(0)[0, 0]
+    R = rp.max() - rp.min()
+    assert np.abs(rg - rp).max() <= 1e-3 * R
+    assert total_variation_2d(rg) <= 1.01 * total_variation_2d(rp)
+    assert envelope_excess_2d(rg, rp) <= 1e-3 * R
+    assert gated.get_flags(0).mean() < 0.5
+
+
+def test_gate_speeds_up_2d_runs(trained):
+    """The point of the gate: on a 2D problem with shocks and smooth regions
+    (four-quadrant, 512^2, 20 steps) the learned gate runs at least 1.1x the
+    plain throughput (about 1.25x measured), best of three each."""
+    import time
+    params = trained[2]
+    n = 512
+    m = [S.Mesh.rect(n, n, 0.0, 1.0, 0.0, 1.0, S.BC_TRANSMISSIVE, S.BC_TRANSMISSIVE)]
+    st = WL.four_quadrant(n, quads_of(11, 1))
+
+    def best(params_):
+        s = S.Solver(m, params_)
+        if params_.weights == S.W_LEARNED:
+            s.gate_load(params)
+        s.set_state(0, st)
+        init = s.state.clone()
+        times = []
+        for _ in range(4):
+            s.state.copy_(init)
+            s.set_times(0.0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            k = s.advance_to(1.0, max_steps=20)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            assert k[0] == 20
+        return min(times[1:])
+
+    t_plain = best(S.Params.make(eq=S.EULER))
+    t_gated = best(S.Params.make(eq=S.EULER, weights=S.W_LEARNED, gate_threshold=0.05))
+    assert t_plain / t_gated >= 1.1, (t_plain, t_gated)

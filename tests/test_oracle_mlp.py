@@ -160,3 +160,45 @@ def test_smooth_data_have_no_labels():
     for n in (40, 100):
         st = WL.density_wave_1d(n)
         assert not O.gate_labels1d(O.Config(eq=O.EULER), st, 2.0 / n, 0.999).any()
+
+
+def test_2d_features_on_y_independent_data_are_the_1d_ones():
+    """With v = 0 and nothing varying in y, the features along x of every row
+    are the 1D features of (rho, m_x, E); along y every shape is zero."""
+    from paper_2304_09724_amd import workloads as WL
+    n, ny, dx, dy = 20, 4, 0.1, 0.3
+    rho = 1 + 0.3 * np.sin(np.arange(n) * 0.7)
+    u = 0.2 + 0.1 * np.cos(np.arange(n))
+    p = 1 + 0.2 * np.sin(np.arange(n) * 1.3)
+    V = np.random.default_rng(1).normal(size=(3, n))
+    st1 = euler_state(rho, u, p, V)
+    st2 = np.zeros((4, 4, ny, n))
+    for qd in range(2):
+        for k2, k1 in ((0, 0), (1, 1), (3, 2)):
+            st2[qd, k2] = st1[qd, k1][None, :]
+    cfg1 = O.Config(eq=O.EULER, bc=TR)
+    cfg2 = O.Config(eq=O.EULER, bc=(O.BC_TRANSMISSIVE, O.BC_TRANSMISSIVE, O.BC_PERIODIC,
+                                    O.BC_PERIODIC))
+    f1 = O.gate_features1d(cfg1, st1, dx)
+    fx = O.gate_features2d(cfg2, st2, dx, dy, 0)
+    fy = O.gate_features2d(cfg2, st2, dx, dy, 1)
+    for j in range(ny):
+        np.testing.assert_allclose(fx[j], f1, rtol=1e-13, atol=1e-15)
+    shape = [0, 1, 2, 3, 5, 6, 7, 8, 10, 11, 12, 13]
+    np.testing.assert_array_equal(fy[:, :, shape], 0.0)
+    np.testing.assert_array_equal(fy[:, :, 15], 0.0)       # no normal velocity in y
+
+
+def test_2d_features_transpose():
+    """Features along y of a state equal the features along x of its
+    transpose (x <-> y, m_x <-> m_y, V <-> Y), including ghost cells."""
+    rng = np.random.default_rng(2)
+    nx, ny = 7, 5
+    st = rng.uniform(0.5, 1.5, size=(4, 4, ny, nx))
+    st[0, 3] += 3.0                                       # keep the pressure positive
+    tr = np.ascontiguousarray(st.transpose(0, 1, 3, 2))[[0, 2, 1, 3]][:, [0, 2, 1, 3]]
+    bc = (O.BC_TRANSMISSIVE, O.BC_PERIODIC, O.BC_REFLECTIVE, O.BC_TRANSMISSIVE)
+    bct = (bc[2], bc[3], bc[0], bc[1])
+    fy = O.gate_features2d(O.Config(eq=O.EULER, bc=bc), st, 0.1, 0.2, 1)
+    fxt = O.gate_features2d(O.Config(eq=O.EULER, bc=bct), tr, 0.2, 0.1, 0)
+    np.testing.assert_allclose(fy, fxt.transpose(1, 0, 2), rtol=1e-13, atol=1e-15)
