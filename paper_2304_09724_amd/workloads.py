@@ -231,16 +231,16 @@ def density_wave_2d(nx: int, ny: int | None = None, t: float = 0.0, gamma=GAMMA,
 
 
 def density_wave_2d_exact_rho(nx, ny=None, t=0.0, L=2.0):
-    """Exact density cell averages (closed form) of the 2D density wave."""
+    """Exact density cell averages (closed form) of the 2D density wave: the
+    average of sin(pi (x + y)) over a cell is
+    4 sin(pi dx/2) sin(pi dy/2) sin(pi (xc + yc)) / (pi^2 dx dy), free of the
+    cancellation of a corner difference on fine meshes."""
     ny = nx if ny is None else ny
-    ex = np.linspace(0.0, L, nx + 1) - t
-    ey = np.linspace(0.0, L, ny + 1) - t
     dx, dy = L / nx, L / ny
-    F = lambda x, y: -np.sin(np.pi * (x + y)) / np.pi ** 2
-    X0, X1 = ex[None, :-1], ex[None, 1:]
-    Y0, Y1 = ey[:-1, None], ey[1:, None]
-    s = F(X1, Y1) - F(X0, Y1) - F(X1, Y0) + F(X0, Y0)
-    return 1.0 + 0.2 * s / (dx * dy)
+    xc = (np.arange(nx) + 0.5) * dx - t
+    yc = (np.arange(ny) + 0.5) * dy - t
+    k = 4.0 * np.sin(np.pi * dx / 2) * np.sin(np.pi * dy / 2) / (np.pi ** 2 * dx * dy)
+    return 1.0 + 0.2 * k * np.sin(np.pi * (xc[None, :] + yc[:, None]))
 
 
 def isentropic_vortex(n: int, t: float = 0.0, gamma=GAMMA, L=10.0):
@@ -280,18 +280,40 @@ def four_quadrant(n: int, quads, gamma=GAMMA):
 def shock_sine_2d(nx: int, ny: int, gamma=GAMMA):
     """Mach-3 shock moving right into rho = 1 + 0.2 sin(5x) sin(3y) at rest,
     p = 1, on (-5,5) x (0, 2pi/3) (the 2D shock/sine workload; post-shock
-    state of sec. 5, Shu-Osher example)."""
-    post = (3.857143, 2.629369, 0.0, 10.333333)
-
-    def fun(x, y, side):
-        left = np.asarray(side) < 0
-        rho = np.where(left, post[0], 1.0 + 0.2 * np.sin(5 * x) * np.sin(3 * y))
-        u = np.where(left, post[1], 0.0)
-        v = np.zeros_like(rho)
-        p = np.where(left, post[3], 1.0)
-        return prim_to_cons(rho, u, p, v, gamma)
-
-    return averages_2d(fun, -5.0, 5.0, 0.0, 2.0 * np.pi / 3.0, nx, ny, xbreak=-4.0)
+    state of sec. 5, Shu-Osher example).  Exact averages in closed form (the
+    field is separable): W, and V, Y, Z as differences of edge and corner
+    values; the cell holding x = -4 splits into its post-shock and its
+    sine part, and its V carries the jump."""
+    post = prim_to_cons(3.857143, 2.629369, 10.333333, 0.0, gamma)
+    x0, x1, y0, y1, xs = -5.0, 5.0, 0.0, 2.0 * np.pi / 3.0, -4.0
+    ex, ey = np.linspace(x0, x1, nx + 1), np.linspace(y0, y1, ny + 1)
+    dx, dy = (x1 - x0) / nx, (y1 - y0) / ny
+    a, b = ex[:-1], ex[1:]
+    lo = np.clip(xs, a, b)                            # start of the sine part
+    f_sine = (b - lo) / dx                            # its share of the cell
+    # x integrals of the sine part over [lo, b] / dx, and edge values
+    Sx = (np.cos(5 * lo) - np.cos(5 * b)) / (5 * dx)
+    # edge values: an edge left of the shock (or on it, for the cell to its
+    # left) belongs to the post-shock part
+    sin_b = np.where(b > xs, np.sin(5 * b), 0.0)
+    sin_a = np.where(a >= xs, np.sin(5 * a), 0.0)
+    Sy = (np.cos(3 * ey[:-1]) - np.cos(3 * ey[1:])) / (3 * dy)
+    Dy = (np.sin(3 * ey[1:]) - np.sin(3 * ey[:-1])) / dy
+    rest = prim_to_cons(1.0, 0.0, 1.0, 0.0, gamma)    # the field without its density wave
+    W = np.empty((4, ny, nx))
+    V, Y, Z = (np.zeros((4, ny, nx)) for _ in range(3))
+    for c in range(4):
+        W[c] = (1.0 - f_sine)[None, :] * post[c] + f_sine[None, :] * rest[c]
+    W[0] += 0.2 * Sx[None, :] * Sy[:, None]
+    # x-derivative averages: (value at b - value at a) / dx, with the jump
+    for c in range(4):
+        va = np.where(a < xs, post[c], rest[c])
+        vb = np.where(b > xs, rest[c], post[c])
+        V[c] = ((vb - va) / dx)[None, :] + np.zeros((ny, 1))
+    V[0] += 0.2 * ((sin_b - sin_a) / dx)[None, :] * Sy[:, None]
+    Y[0] = 0.2 * Sx[None, :] * Dy[:, None]
+    Z[0] = 0.2 * ((sin_b - sin_a) / dx)[None, :] * Dy[:, None]
+    return np.ascontiguousarray(np.stack([W, V, Y, Z]))
 
 
 # ---------------------------------------------------------------------------
