@@ -220,6 +220,12 @@ shw_status shw_mlp_grad(const float *d_X, const float *d_y, int n, const float *
 shw_status shw_mlp_adam(float *d_params, const float *d_grad, float *d_m, float *d_v, int step,
                         float lr, void *hip_stream);
 
+/* 2D: shw_advance_to runs the steps in chunks of 8 on the device and, by
+ * default, replays each full chunk as one HIP graph captured at the first
+ * use (kernels only, no memory operations); enable = 0 launches the kernels
+ * one by one instead.  Results are identical either way. */
+shw_status shw_set_graphs(shw_ctx *ctx, int enable);
+
 /* Per-instance status (host array of n_inst): SHW_OK, or SHW_ENONPHYS for an
  * instance that met a non-physical state and stopped.  Synchronising. */
 shw_status shw_instance_status(shw_ctx *ctx, int *codes);

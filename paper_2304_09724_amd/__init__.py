@@ -102,6 +102,7 @@ def lib():
         L.shw_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, vp]
         L.shw_set_flags.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8)]
         L.shw_get_flags.argtypes = [vp, ctypes.c_int, vp]
+        L.shw_set_graphs.argtypes = [vp, ctypes.c_int]
         L.shw_status_detail.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_char_p,
                                         ctypes.c_size_t]
         _lib = L
@@ -282,6 +283,10 @@ class Solver:
         lab = torch.empty(cells, dtype=torch.uint8, device=self.device)
         self._check(lib().shw_gate_data(self.ctx, float(level), _vp(f), _vp(lab)))
         return f, lab
+
+    def set_graphs(self, enable):
+        """2D: replay chunks of steps as a captured HIP graph (default) or not."""
+        self._check(lib().shw_set_graphs(self.ctx, int(bool(enable))))
 
     def get_flags(self, i):
         """Per-cell flags of instance i as the last step used them ((ny, nx)

@@ -116,6 +116,16 @@ struct shw_ctx {
     bool gate_loaded = false;
     int bad_instance = -1;
     std::string msg;
+    // 2D: a chunk of steps captured once as a HIP graph and replayed
+    bool use_graphs = true;
+    hipGraphExec_t chunk_exec = nullptr;
+    hipStream_t capture_stream = nullptr;   // capture cannot run on the null stream
+
+    ~shw_ctx()
+    {
+        if (chunk_exec) (void)hipGraphExecDestroy(chunk_exec);
+        if (capture_stream) (void)hipStreamDestroy(capture_stream);
+    }
 
     template <class T> T *at(size_t o) { return reinterpret_cast<T *>(ws + o); }
     double *alt() { return at<double>(lay.alt); }
@@ -461,10 +471,39 @@ shw_status shw_step(shw_ctx *c, const double *dt)
 }
 
 // 2D time loop: steps run on the device in chunks; the host only polls the
-// number of instances still running between chunks.
+// number of instances still running between chunks.  A full chunk is one
+// replay, on the context's stream, of a HIP graph captured on the first call
+// on a private stream (its kernels take only device pointers fixed for the
+// context, so every replay does the same as launching them; the graph holds
+// kernels only).
+constexpr int CHUNK_STEPS = 8;
+
+static shw_status chunk_graph(shw_ctx *c, const Step2D &S)
+{
+    if (c->chunk_exec) return SHW_OK;
+    shw_status s = SHW_OK;
+    if (!c->capture_stream)
+        s = c->hip(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking),
+                   "capture stream");
+    if (s == SHW_OK)
+        s = c->hip(hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal),
+                   "begin capture");
+    if (s != SHW_OK) return s;
+    hipError_t launch = hipSuccess;
+    for (int j = 0; j < CHUNK_STEPS && launch == hipSuccess; ++j)
+        launch = launch_step2d(c->params.eq, S, c->dp, 0, c->tiles2d, c->capture_stream);
+    hipGraph_t g = nullptr;
+    s = c->hip(hipStreamEndCapture(c->capture_stream, &g), "end capture");
+    if (s == SHW_OK) s = c->hip(launch, "capture step2d");
+    if (s == SHW_OK) s = c->hip(hipGraphInstantiate(&c->chunk_exec, g, nullptr, nullptr, 0),
+                                "instantiate");
+    if (g) (void)hipGraphDestroy(g);
+    if (s != SHW_OK) c->chunk_exec = nullptr;
+    return s;
+}
+
 static shw_status advance2d(shw_ctx *c, long long max_steps)
 {
-    constexpr int CHUNK_STEPS = 8;
     Step2D S = step2d_args(c);
     std::vector<long long> budget(c->n_inst, max_steps);
     shw_status s = c->hip(hipMemcpyAsync(S.steps_left, budget.data(), c->n_inst * sizeof(long long),
@@ -474,9 +513,16 @@ static shw_status advance2d(shw_ctx *c, long long max_steps)
     if (s != SHW_OK) return s;
     for (long long done = 0; done < max_steps;) {
         const int k = (int)std::min<long long>(CHUNK_STEPS, max_steps - done);
-        for (int j = 0; j < k; ++j) {
-            s = c->hip(launch_step2d(c->params.eq, S, c->dp, 0, c->tiles2d, c->stream), "step2d");
+        if (k == CHUNK_STEPS && c->use_graphs) {
+            s = chunk_graph(c, S);
+            if (s == SHW_OK) s = c->hip(hipGraphLaunch(c->chunk_exec, c->stream), "graph launch");
             if (s != SHW_OK) return s;
+        } else {
+            for (int j = 0; j < k; ++j) {
+                s = c->hip(launch_step2d(c->params.eq, S, c->dp, 0, c->tiles2d, c->stream),
+                           "step2d");
+                if (s != SHW_OK) return s;
+            }
         }
         done += k;
         int active = 0;
@@ -487,6 +533,13 @@ static shw_status advance2d(shw_ctx *c, long long max_steps)
         if (active == 0) break;
     }
     return c->hip(launch_settle2d(S, c->m, c->stream), "settle");
+}
+
+shw_status shw_set_graphs(shw_ctx *c, int enable)
+{
+    if (!c) return SHW_EINVAL;
+    c->use_graphs = enable != 0;
+    return SHW_OK;
 }
 
 shw_status shw_advance_to(shw_ctx *c, const double *T, long long max_steps, long long *steps_out)

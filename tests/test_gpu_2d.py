@@ -180,3 +180,41 @@ def test_transpose_symmetry_on_gpu():
     b = s.get_state(0)
     bt = b[[0, 2, 1, 3]][:, [0, 2, 1, 3]].transpose(0, 1, 3, 2)
     assert rel_err(a, bt) < 1e-12
+
+
+@pytest.mark.parametrize("weights", [S.W_NONLINEAR, S.W_LEARNED])
+def test_graph_replays_match_eager_launches(weights):
+    """The 2D time loop's captured chunk (8 steps as one HIP graph) against
+    the same kernels launched one by one: each call below is exactly one
+    replay, checked bit for bit, with eager work of the program (state round
+    trips, a torch op, synchronisations) between the replays."""
+    import torch
+    from paper_2304_09724_amd import gate as GT
+    sizes = [24, 40, 32]
+    insts = WL.four_quadrant_batch(count=3, seed=11)
+    meshes = [S.Mesh.rect(n, n, 0.0, 1.0, 0.0, 1.0, S.BC_TRANSMISSIVE, S.BC_TRANSMISSIVE)
+              for n in sizes]
+    prm = S.Params.make(eq=S.EULER, weights=weights, gate_threshold=0.3)
+    a, b = S.Solver(meshes, prm), S.Solver(meshes, prm)
+    b.set_graphs(False)
+    for s in (a, b):
+        if weights == S.W_LEARNED:
+            s.gate_load(GT.init_params(3))
+        for i, (n, d) in enumerate(zip(sizes, insts)):
+            s.set_state(i, WL.four_quadrant(n, d.quads))
+    for rep in range(6):
+        ka = a.advance_to(1.0, max_steps=8, raise_nonphysical=False)
+        kb = b.advance_to(1.0, max_steps=8, raise_nonphysical=False)
+        assert np.array_equal(ka, kb), rep
+        for i in range(len(sizes)):
+            assert np.array_equal(a.get_state(i), b.get_state(i)), (rep, i)
+        ta, sa = a.times()
+        tb, sb = b.times()
+        assert np.array_equal(ta, tb) and np.array_equal(sa, sb)
+        # eager work between replays
+        x = a.get_state(1)
+        a.set_state(1, x)
+        b.set_state(1, b.get_state(1))
+        a.state.mul_(1.0)
+        torch.cuda.synchronize()
+    assert ka.sum() > 0
