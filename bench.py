@@ -257,6 +257,13 @@ def main():
         solver.set_times(zeros)
         return solver.advance_to(T, raise_nonphysical=False)
 
+    # tile variant from the project's autotuner (8 steps of every instance per
+    # variant, untimed here)
+    solver.state.copy_(init)
+    solver.set_times(zeros)
+    tile, tile_ms = solver.autotune(steps=8)
+    log(f"autotuner: variant {tile} (ms per variant {tile_ms})")
+
     log(f"warmup x{args.warmup} ...")
     for _ in range(args.warmup):
         one_step()
@@ -308,7 +315,9 @@ def main():
                                           "positivity limiter, as in the paper) meets a "
                                           "non-physical state stop there; only the cell-"
                                           "updates actually performed are counted",
-                      "parallelism": "single GPU, one persistent launch"},
+                      "parallelism": "single GPU, one persistent launch",
+                      "tile": {"variant": tile, "threads_per_instance": [128, 256, 512][tile],
+                               "autotune_ms_8_steps": [round(x, 3) for x in tile_ms]}},
            "roofline": roofline}
     if args.copy_check > 0:
         src = torch.ones(args.copy_check // 8, dtype=torch.float64, device="cuda:0")

@@ -226,6 +226,22 @@ shw_status shw_mlp_adam(float *d_params, const float *d_grad, float *d_m, float 
  * one by one instead.  Results are identical either way. */
 shw_status shw_set_graphs(shw_ctx *ctx, int enable);
 
+/* Tile variant of the kernels (results are identical for all of them):
+ * 1D, the persistent workgroup that advances one instance has 128, 256 or
+ * 512 threads (2, 4 or 8 waves sharing its 62-cell chunks) for variant 0, 1,
+ * 2 (default 1); 2D, a sweep tile is 1, 2 or 4 lines of 60 cells (default
+ * 2, i.e. 4 lines).  SHW_EINVAL for another value. */
+shw_status shw_set_tile(shw_ctx *ctx, int variant);
+shw_status shw_get_tile(shw_ctx *ctx, int *variant);
+
+/* Autotuner: times `steps` CFL steps of every instance (no end time within
+ * reach) for each tile variant, warm, on the context's own batch, keeps the
+ * fastest (written to *best; per-variant milliseconds to ms[3], may be NULL)
+ * and leaves state and times as they were.  d_scratch: caller-owned device
+ * buffer of sum(shw_state_doubles) doubles for the saved state.  Steps
+ * 1..100000.  Synchronising. */
+shw_status shw_autotune(shw_ctx *ctx, double *d_scratch, int steps, int *best, float *ms);
+
 /* Per-instance status (host array of n_inst): SHW_OK, or SHW_ENONPHYS for an
  * instance that met a non-physical state and stopped.  Synchronising. */
 shw_status shw_instance_status(shw_ctx *ctx, int *codes);

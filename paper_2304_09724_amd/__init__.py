@@ -103,6 +103,10 @@ def lib():
         L.shw_set_flags.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint8)]
         L.shw_get_flags.argtypes = [vp, ctypes.c_int, vp]
         L.shw_set_graphs.argtypes = [vp, ctypes.c_int]
+        L.shw_set_tile.argtypes = [vp, ctypes.c_int]
+        L.shw_get_tile.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
+        L.shw_autotune.argtypes = [vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                   ctypes.POINTER(ctypes.c_float)]
         L.shw_status_detail.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_char_p,
                                         ctypes.c_size_t]
         _lib = L
@@ -287,6 +291,25 @@ class Solver:
     def set_graphs(self, enable):
         """2D: replay chunks of steps as a captured HIP graph (default) or not."""
         self._check(lib().shw_set_graphs(self.ctx, int(bool(enable))))
+
+    def set_tile(self, variant):
+        self._check(lib().shw_set_tile(self.ctx, int(variant)))
+
+    def get_tile(self):
+        v = ctypes.c_int()
+        self._check(lib().shw_get_tile(self.ctx, ctypes.byref(v)))
+        return v.value
+
+    def autotune(self, steps=8):
+        """Time each tile variant for `steps` steps on this batch, keep the
+        fastest; state and times are left unchanged.  Returns (variant,
+        milliseconds per variant)."""
+        scratch = self.torch.empty_like(self.state)
+        best = ctypes.c_int()
+        ms = (ctypes.c_float * 3)()
+        self._check(lib().shw_autotune(self.ctx, ctypes.c_void_p(scratch.data_ptr()), int(steps),
+                                       ctypes.byref(best), ms))
+        return best.value, list(ms)
 
     def get_flags(self, i):
         """Per-cell flags of instance i as the last step used them ((ny, nx)

@@ -79,11 +79,11 @@ struct Step2D {
     float gate_logit_min;      // cells with logit >= this take the full reconstruction
 };
 
-int sweep2d_tiles(int n_sweep, int n_trans);
+int sweep2d_tiles(int n_sweep, int n_trans, int lines);
 hipError_t launch_speed2d(int eq, const Step2D &S, const DevParams &P, int use_parity,
                           hipStream_t stream);
 hipError_t launch_step2d(int eq, const Step2D &S, const DevParams &P, int fixed,
-                         const int total_tiles[2], hipStream_t stream);
+                         const int total_tiles[2], int lines, hipStream_t stream);
 hipError_t launch_settle2d(const Step2D &S, int m, hipStream_t stream);
 
 hipError_t launch_gate_data1d(const Inst1D *inst, int n_inst, int max_n, const double *state,
@@ -96,9 +96,9 @@ hipError_t launch_mlp_grad(const float *X, const float *y, int n, const float *p
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, int t, float lr,
                        hipStream_t stream);
 
-hipError_t launch_loop1d(int eq, const Loop1D &L, const DevParams &P, int grid,
+hipError_t launch_loop1d(int eq, const Loop1D &L, const DevParams &P, int grid, int variant,
                          hipStream_t stream);
-int loop1d_max_blocks(int eq);
+int loop1d_max_blocks(int eq, int variant);
 hipError_t launch_dt1d(int eq, const Inst1D *inst, int n_inst, const double *state,
                        const DevParams &P, double *dt_out, hipStream_t stream);
 

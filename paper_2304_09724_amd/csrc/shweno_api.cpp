@@ -60,6 +60,11 @@ size_t state_doubles(const shw_mesh *m, int eq)
     return (size_t)(m->dim == 1 ? 2 : 4) * ncomp(eq, m->dim) * (size_t)m->nx * m->ny;
 }
 
+// Tile variants the autotuner chooses between: 1D, 128 / 256 / 512 threads
+// (2, 4, 8 waves) per instance; 2D, 1 / 2 / 4 lines of 60 cells per tile.
+constexpr int N_TILE_VARIANTS = 3;
+constexpr int lines2d(int v) { return 1 << v; }
+
 // Device workspace carved out of the caller's buffer.
 struct Layout {
     size_t alt = 0, inst = 0, order = 0, queue = 0, ist = 0, t_end = 0, dt = 0,
@@ -85,8 +90,8 @@ Layout make_layout(const shw_mesh *meshes, int n_inst, const shw_params *p)
     L.t_end = take((size_t)n_inst * sizeof(double));
     L.dt = take((size_t)n_inst * sizeof(double));
     L.flags = take(cells);
-    L.tiles0 = take((size_t)(n_inst + 1) * sizeof(int));
-    L.tiles1 = take((size_t)(n_inst + 1) * sizeof(int));
+    L.tiles0 = take((size_t)N_TILE_VARIANTS * (n_inst + 1) * sizeof(int));
+    L.tiles1 = take((size_t)N_TILE_VARIANTS * (n_inst + 1) * sizeof(int));
     L.parity = take((size_t)n_inst * sizeof(int));
     L.last = take((size_t)n_inst * sizeof(int));
     L.dt_fixed = take((size_t)n_inst * sizeof(double));
@@ -112,7 +117,8 @@ struct shw_ctx {
     Layout lay;
     hipStream_t stream = nullptr;
     int grid1d = 1;
-    int tiles2d[2] = {0, 0};
+    int variant = -1;                   // tile variant in use (set at create)
+    int tiles2d[N_TILE_VARIANTS][2] = {};
     bool gate_loaded = false;
     int bad_instance = -1;
     std::string msg;
@@ -201,7 +207,8 @@ shw_status shw_create(const shw_mesh *meshes, int n_inst, const shw_params *para
     long long o = 0, co = 0;
     std::vector<Inst1D> i1;
     std::vector<Inst2D> i2;
-    std::vector<int> toff0(1, 0), toff1(1, 0);
+    std::vector<int> toff[N_TILE_VARIANTS][2];
+    for (auto &tv : toff) tv[0] = tv[1] = std::vector<int>(1, 0);
     for (int i = 0; i < n_inst; ++i) {
         const shw_mesh &m = meshes[i];
         c->off.push_back(o);
@@ -225,8 +232,10 @@ shw_status shw_create(const shw_mesh *meshes, int n_inst, const shw_params *para
             d.dx = (m.x1 - m.x0) / m.nx;
             d.dy = (m.y1 - m.y0) / m.ny;
             i2.push_back(d);
-            toff0.push_back(toff0.back() + sweep2d_tiles(m.nx, m.ny));
-            toff1.push_back(toff1.back() + sweep2d_tiles(m.ny, m.nx));
+            for (int v = 0; v < N_TILE_VARIANTS; ++v) {
+                toff[v][0].push_back(toff[v][0].back() + sweep2d_tiles(m.nx, m.ny, lines2d(v)));
+                toff[v][1].push_back(toff[v][1].back() + sweep2d_tiles(m.ny, m.nx, lines2d(v)));
+            }
         }
         o += (long long)state_doubles(&m, params->eq);
         co += (long long)m.nx * m.ny;
@@ -242,18 +251,24 @@ shw_status shw_create(const shw_mesh *meshes, int n_inst, const shw_params *para
     if (c->dim == 1) {
         s = c->hip(hipMemcpyAsync(c->ws + c->lay.inst, i1.data(), i1.size() * sizeof(Inst1D),
                                   hipMemcpyHostToDevice, c->stream), "copy instances");
-        c->grid1d = loop1d_max_blocks(params->eq);
+        c->variant = 1;
+        c->grid1d = loop1d_max_blocks(params->eq, c->variant);
     } else {
         s = c->hip(hipMemcpyAsync(c->ws + c->lay.inst, i2.data(), i2.size() * sizeof(Inst2D),
                                   hipMemcpyHostToDevice, c->stream), "copy instances");
-        if (s == SHW_OK)
-            s = c->hip(hipMemcpyAsync(c->ws + c->lay.tiles0, toff0.data(), toff0.size() * sizeof(int),
-                                      hipMemcpyHostToDevice, c->stream), "copy tiles");
-        if (s == SHW_OK)
-            s = c->hip(hipMemcpyAsync(c->ws + c->lay.tiles1, toff1.data(), toff1.size() * sizeof(int),
-                                      hipMemcpyHostToDevice, c->stream), "copy tiles");
-        c->tiles2d[0] = toff0.back();
-        c->tiles2d[1] = toff1.back();
+        const size_t per = (size_t)(n_inst + 1);
+        for (int v = 0; v < N_TILE_VARIANTS && s == SHW_OK; ++v) {
+            s = c->hip(hipMemcpyAsync(c->ws + c->lay.tiles0 + v * per * sizeof(int), toff[v][0].data(),
+                                      per * sizeof(int), hipMemcpyHostToDevice, c->stream),
+                       "copy tiles");
+            if (s == SHW_OK)
+                s = c->hip(hipMemcpyAsync(c->ws + c->lay.tiles1 + v * per * sizeof(int),
+                                          toff[v][1].data(), per * sizeof(int),
+                                          hipMemcpyHostToDevice, c->stream), "copy tiles");
+            c->tiles2d[v][0] = toff[v][0].back();
+            c->tiles2d[v][1] = toff[v][1].back();
+        }
+        c->variant = 2;
     }
     if (s == SHW_OK)
         s = c->hip(hipMemsetAsync(c->ws + c->lay.parity, 0, n_inst * sizeof(int), c->stream),
@@ -402,8 +417,8 @@ static Step2D step2d_args(shw_ctx *c)
     Step2D S{};
     S.inst = c->at<Inst2D>(c->lay.inst);
     S.n_inst = c->n_inst;
-    S.tile_off[0] = c->at<int>(c->lay.tiles0);
-    S.tile_off[1] = c->at<int>(c->lay.tiles1);
+    S.tile_off[0] = c->at<int>(c->lay.tiles0) + (size_t)c->variant * (c->n_inst + 1);
+    S.tile_off[1] = c->at<int>(c->lay.tiles1) + (size_t)c->variant * (c->n_inst + 1);
     S.state = c->state;
     S.alt = c->alt();
     S.parity = c->at<int>(c->lay.parity);
@@ -454,7 +469,8 @@ shw_status shw_step(shw_ctx *c, const double *dt)
                                              c->n_inst * sizeof(double), hipMemcpyHostToDevice,
                                              c->stream), "step dt");
         if (s != SHW_OK) return s;
-        s = c->hip(launch_step2d(c->params.eq, S, c->dp, 1, c->tiles2d, c->stream), "step2d");
+        s = c->hip(launch_step2d(c->params.eq, S, c->dp, 1, c->tiles2d[c->variant],
+                                 lines2d(c->variant), c->stream), "step2d");
         if (s != SHW_OK) return s;
         return c->hip(launch_settle2d(S, c->m, c->stream), "settle");
     }
@@ -467,7 +483,7 @@ shw_status shw_step(shw_ctx *c, const double *dt)
     L.t_end = nullptr;
     L.max_steps = 1;
     int grid = std::min(c->grid1d, c->n_inst);
-    return c->hip(launch_loop1d(c->params.eq, L, c->dp, grid, c->stream), "step");
+    return c->hip(launch_loop1d(c->params.eq, L, c->dp, grid, c->variant, c->stream), "step");
 }
 
 // 2D time loop: steps run on the device in chunks; the host only polls the
@@ -491,7 +507,8 @@ static shw_status chunk_graph(shw_ctx *c, const Step2D &S)
     if (s != SHW_OK) return s;
     hipError_t launch = hipSuccess;
     for (int j = 0; j < CHUNK_STEPS && launch == hipSuccess; ++j)
-        launch = launch_step2d(c->params.eq, S, c->dp, 0, c->tiles2d, c->capture_stream);
+        launch = launch_step2d(c->params.eq, S, c->dp, 0, c->tiles2d[c->variant], lines2d(c->variant),
+                               c->capture_stream);
     hipGraph_t g = nullptr;
     s = c->hip(hipStreamEndCapture(c->capture_stream, &g), "end capture");
     if (s == SHW_OK) s = c->hip(launch, "capture step2d");
@@ -519,8 +536,8 @@ static shw_status advance2d(shw_ctx *c, long long max_steps)
             if (s != SHW_OK) return s;
         } else {
             for (int j = 0; j < k; ++j) {
-                s = c->hip(launch_step2d(c->params.eq, S, c->dp, 0, c->tiles2d, c->stream),
-                           "step2d");
+                s = c->hip(launch_step2d(c->params.eq, S, c->dp, 0, c->tiles2d[c->variant],
+                                         lines2d(c->variant), c->stream), "step2d");
                 if (s != SHW_OK) return s;
             }
         }
@@ -535,11 +552,108 @@ static shw_status advance2d(shw_ctx *c, long long max_steps)
     return c->hip(launch_settle2d(S, c->m, c->stream), "settle");
 }
 
+static shw_status run_to(shw_ctx *c, const double *T, long long max_steps);
+
+shw_status shw_set_tile(shw_ctx *c, int variant)
+{
+    if (!c || variant < 0 || variant >= N_TILE_VARIANTS) return SHW_EINVAL;
+    if (variant == c->variant) return SHW_OK;
+    if (c->chunk_exec) {                  // the captured chunk holds the old tiles
+        (void)hipGraphExecDestroy(c->chunk_exec);
+        c->chunk_exec = nullptr;
+    }
+    c->variant = variant;
+    if (c->dim == 1) c->grid1d = loop1d_max_blocks(c->params.eq, variant);
+    return SHW_OK;
+}
+
+shw_status shw_get_tile(shw_ctx *c, int *variant)
+{
+    if (!c || !variant) return SHW_EINVAL;
+    *variant = c->variant;
+    return SHW_OK;
+}
+
+shw_status shw_autotune(shw_ctx *c, double *d_scratch, int steps, int *best, float *ms)
+{
+    if (!c || !d_scratch || steps < 1 || steps > 100000) return SHW_EINVAL;
+    if (c->params.weights == SHW_W_LEARNED && !c->gate_loaded)
+        return c->fail(SHW_ESTATE, "learned gate not loaded");
+    size_t nd = 0;
+    for (const auto &m : c->meshes) nd += state_doubles(&m, c->params.eq);
+    std::vector<InstState> saved;
+    shw_status s = read_ist(c, saved);
+    if (s == SHW_OK)
+        s = c->hip(hipMemcpyAsync(d_scratch, c->state, nd * sizeof(double), hipMemcpyDeviceToDevice,
+                                  c->stream), "save state");
+    if (s != SHW_OK) return s;
+    auto restore = [&]() {
+        shw_status r = c->hip(hipMemcpyAsync(c->state, d_scratch, nd * sizeof(double),
+                                             hipMemcpyDeviceToDevice, c->stream), "restore state");
+        if (r == SHW_OK)
+            r = c->hip(hipMemcpyAsync(c->ist(), saved.data(), c->n_inst * sizeof(InstState),
+                                      hipMemcpyHostToDevice, c->stream), "restore times");
+        return r;
+    };
+    // every instance steps: no end time within reach
+    const std::vector<double> far(c->n_inst, 1e300);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    s = c->hip(hipEventCreate(&e0), "event");
+    if (s == SHW_OK) s = c->hip(hipEventCreate(&e1), "event");
+    const int start = c->variant;
+    float t_best = 0.0f;
+    int v_best = start;
+    for (int v = 0; v < N_TILE_VARIANTS && s == SHW_OK; ++v) {
+        s = shw_set_tile(c, v);
+        float t = 0.0f;
+        for (int rep = 0; rep < 2 && s == SHW_OK; ++rep) {       // warm (and capture), timed
+            s = restore();
+            if (s == SHW_OK) s = c->hip(hipEventRecord(e0, c->stream), "event");
+            if (s == SHW_OK) s = run_to(c, far.data(), steps);
+            if (s == SHW_OK) s = c->hip(hipEventRecord(e1, c->stream), "event");
+            if (s == SHW_OK) s = c->hip(hipEventSynchronize(e1), "event sync");
+            if (s == SHW_OK) s = c->hip(hipEventElapsedTime(&t, e0, e1), "event time");
+        }
+        if (s != SHW_OK) break;
+        if (ms) ms[v] = t;
+        if (v == 0 || t < t_best) {
+            t_best = t;
+            v_best = v;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    shw_status r = restore();
+    if (s == SHW_OK) s = r;
+    if (s == SHW_OK) s = c->hip(hipStreamSynchronize(c->stream), "autotune sync");
+    const shw_status t = shw_set_tile(c, s == SHW_OK ? v_best : start);
+    if (s == SHW_OK) s = t;
+    if (s == SHW_OK && best) *best = v_best;
+    return s;
+}
+
 shw_status shw_set_graphs(shw_ctx *c, int enable)
 {
     if (!c) return SHW_EINVAL;
     c->use_graphs = enable != 0;
     return SHW_OK;
+}
+
+// CFL steps towards the end times T (host array) with the current tile
+// variant; asynchronous except for the 2D chunk polls.
+static shw_status run_to(shw_ctx *c, const double *T, long long max_steps)
+{
+    double *d_T = c->at<double>(c->lay.t_end);
+    shw_status s = c->hip(hipMemcpyAsync(d_T, T, c->n_inst * sizeof(double), hipMemcpyHostToDevice,
+                                         c->stream), "advance T");
+    if (s != SHW_OK) return s;
+    if (c->dim == 2) return advance2d(c, max_steps);
+    Loop1D L = loop_args(c);
+    L.dt_fixed = nullptr;
+    L.t_end = d_T;
+    L.max_steps = max_steps;
+    int grid = std::min(c->grid1d, c->n_inst);
+    return c->hip(launch_loop1d(c->params.eq, L, c->dp, grid, c->variant, c->stream), "advance");
 }
 
 shw_status shw_advance_to(shw_ctx *c, const double *T, long long max_steps, long long *steps_out)
@@ -552,22 +666,8 @@ shw_status shw_advance_to(shw_ctx *c, const double *T, long long max_steps, long
     std::vector<InstState> before;
     shw_status s = read_ist(c, before);
     if (s != SHW_OK) return s;
-    double *d_T = c->at<double>(c->lay.t_end);
-    s = c->hip(hipMemcpyAsync(d_T, T, c->n_inst * sizeof(double), hipMemcpyHostToDevice,
-                              c->stream), "advance T");
+    s = run_to(c, T, max_steps);
     if (s != SHW_OK) return s;
-    if (c->dim == 2) {
-        s = advance2d(c, max_steps);
-        if (s != SHW_OK) return s;
-    } else {
-    Loop1D L = loop_args(c);
-    L.dt_fixed = nullptr;
-    L.t_end = d_T;
-    L.max_steps = max_steps;
-    int grid = std::min(c->grid1d, c->n_inst);
-    s = c->hip(launch_loop1d(c->params.eq, L, c->dp, grid, c->stream), "advance");
-    if (s != SHW_OK) return s;
-    }
     std::vector<InstState> after;
     s = read_ist(c, after);
     if (s != SHW_OK) return s;

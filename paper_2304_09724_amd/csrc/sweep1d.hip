@@ -60,7 +60,7 @@ __device__ __forceinline__ int flag_cell(int q, int n, int bc_lo, int bc_hi)
     return q;
 }
 
-template <int EQ>
+template <int EQ, int NB>
 __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__restrict__ src,
                                                double *__restrict__ dst, double dt,
                                                const DevParams &P,
@@ -74,7 +74,7 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
     const int nchunk = (n + CHUNK - 1) / CHUNK;
     const double idx = 1.0 / d.dx, dt_dx = dt * idx;
     bool bad = false;
-    for (int ch = wave; ch < nchunk; ch += BLOCK / WAVE) {
+    for (int ch = wave; ch < nchunk; ch += NB / WAVE) {
         const int j = ch * CHUNK + lane - 1;       // this lane's cell, -1..n+61
         const bool live = j <= n;
         // lanes past the end read the last ghost cell and discard the result
@@ -146,17 +146,17 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
     return bad;
 }
 
-template <int EQ>
-__global__ void __launch_bounds__(BLOCK) loop1d_kernel(Loop1D Lp, DevParams P)
+template <int EQ, int NB>
+__global__ void __launch_bounds__(NB) loop1d_kernel(Loop1D Lp, DevParams P)
 {
     constexpr int M = NComp<EQ, 1>::M;
     __shared__ int s_item;
-    __shared__ double s_red[BLOCK / WAVE];
+    __shared__ double s_red[NB / WAVE];
     __shared__ u32x4 s_gate[EQ == EULER ? GATE_LDS_WORDS : 1];
     const int tid = threadIdx.x;
     if (EQ == EULER && P.weights == W_LEARNED) {
         // the packed network, shared by the waves, transposed for the LDS
-        gate_to_lds(Lp.gate, s_gate, tid, BLOCK);
+        gate_to_lds(Lp.gate, s_gate, tid, NB);
         __syncthreads();
     }
     for (;;) {
@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(BLOCK) loop1d_kernel(Loop1D Lp, DevParams P)
                 if (!(st.t < T)) break;
                 // CFL step size from the averages at t_n (block max reduction)
                 double smax = 0.0;
-                for (int j = tid; j < d.n; j += BLOCK) {
+                for (int j = tid; j < d.n; j += NB) {
                     double W[M];
 #pragma unroll
                     for (int c = 0; c < M; ++c) W[c] = A[c * d.n + j];
@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(BLOCK) loop1d_kernel(Loop1D Lp, DevParams P)
                 __syncthreads();
                 smax = s_red[0];
 #pragma unroll
-                for (int w = 1; w < BLOCK / WAVE; ++w) smax = fmax(smax, s_red[w]);
+                for (int w = 1; w < NB / WAVE; ++w) smax = fmax(smax, s_red[w]);
                 __syncthreads();
                 dt = P.cfl * d.dx / smax;
                 if (dt >= T - st.t) { dt = T - st.t; last = true; }
@@ -207,8 +207,8 @@ __global__ void __launch_bounds__(BLOCK) loop1d_kernel(Loop1D Lp, DevParams P)
             // steps of the instance; steps are separated by block barriers, so
             // the decisions one wave stores are seen by the other waves
             gate_since = (k == 0 || (st.steps + k) % Lp.gate_every == 0) ? 0 : gate_since + 1;
-            const bool bad = sweep_instance<EQ>(d, A, B, dt, P, Lp.flags, s_gate, Lp.gate_logit_min,
-                                                gate_since);
+            const bool bad = sweep_instance<EQ, NB>(d, A, B, dt, P, Lp.flags, s_gate,
+                                                    Lp.gate_logit_min, gate_since);
             const int any_bad = __syncthreads_or(bad);
             double *tmp = A; A = B; B = tmp;
             ++k;
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(BLOCK) loop1d_kernel(Loop1D Lp, DevParams P)
         // the current state must end in the caller's buffer
         if (k & 1) {
             double *dst = Lp.state + d.off;
-            for (long long e = tid; e < nd; e += BLOCK) dst[e] = A[e];
+            for (long long e = tid; e < nd; e += NB) dst[e] = A[e];
         }
         if (tid == 0) {
             st.steps += k;
@@ -260,24 +260,45 @@ __global__ void zero_int_kernel(int *p) { *p = 0; }
 
 } // namespace
 
-hipError_t launch_loop1d(int eq, const Loop1D &L, const DevParams &P, int grid,
-                         hipStream_t stream)
+// workgroup size of tile variant v: 2, 4 or 8 waves per instance
+static int loop1d_threads(int v) { return v == 0 ? 128 : v == 2 ? 512 : 256; }
+
+template <int NB>
+static void launch_loop1d_nb(int eq, const Loop1D &L, const DevParams &P, int grid,
+                             hipStream_t stream)
 {
-    zero_int_kernel<<<1, 1, 0, stream>>>(L.queue);
-    if (eq == EULER) loop1d_kernel<EULER><<<grid, BLOCK, 0, stream>>>(L, P);
-    else if (eq == BURG) loop1d_kernel<BURG><<<grid, BLOCK, 0, stream>>>(L, P);
-    else loop1d_kernel<ADV><<<grid, BLOCK, 0, stream>>>(L, P);
-    return hipGetLastError();
+    if (eq == EULER) loop1d_kernel<EULER, NB><<<grid, NB, 0, stream>>>(L, P);
+    else if (eq == BURG) loop1d_kernel<BURG, NB><<<grid, NB, 0, stream>>>(L, P);
+    else loop1d_kernel<ADV, NB><<<grid, NB, 0, stream>>>(L, P);
 }
 
-int loop1d_max_blocks(int eq)
+template <int NB>
+static int loop1d_per_cu(int eq)
 {
     int per_cu = 0;
     hipError_t e;
-    if (eq == EULER) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop1d_kernel<EULER>, BLOCK, 0);
-    else if (eq == BURG) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop1d_kernel<BURG>, BLOCK, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop1d_kernel<ADV>, BLOCK, 0);
-    if (e != hipSuccess || per_cu < 1) per_cu = 1;
+    if (eq == EULER) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop1d_kernel<EULER, NB>, NB, 0);
+    else if (eq == BURG) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop1d_kernel<BURG, NB>, NB, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop1d_kernel<ADV, NB>, NB, 0);
+    return (e != hipSuccess || per_cu < 1) ? 1 : per_cu;
+}
+
+hipError_t launch_loop1d(int eq, const Loop1D &L, const DevParams &P, int grid, int variant,
+                         hipStream_t stream)
+{
+    zero_int_kernel<<<1, 1, 0, stream>>>(L.queue);
+    const int nb = loop1d_threads(variant);
+    if (nb == 128) launch_loop1d_nb<128>(eq, L, P, grid, stream);
+    else if (nb == 512) launch_loop1d_nb<512>(eq, L, P, grid, stream);
+    else launch_loop1d_nb<256>(eq, L, P, grid, stream);
+    return hipGetLastError();
+}
+
+int loop1d_max_blocks(int eq, int variant)
+{
+    const int nb = loop1d_threads(variant);
+    const int per_cu = nb == 128 ? loop1d_per_cu<128>(eq)
+                                 : nb == 512 ? loop1d_per_cu<512>(eq) : loop1d_per_cu<256>(eq);
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);

@@ -4,7 +4,8 @@
 // the device (step size, time, ping-pong parity, done and non-physical
 // flags), so a sequence of steps can be replayed as one HIP graph.
 //
-// A sweep kernel works on tiles of 4 lines x 60 cells: one wave per line
+// A sweep kernel works on tiles of L lines x 60 cells (L = 1, 2 or 4, the
+// tile variant the autotuner picks): one wave per line
 // (a row for the x-sweep, a column for the y-sweep), one lane per cell.  Lane
 // l holds cell c0 + l - 2.  Every lane does stage 1 of its cell (transverse
 // reconstruction, sec. 3.2); lanes 1..62 do stage 2 at each of the four
@@ -98,9 +99,10 @@ __device__ __forceinline__ int find_instance(const int *__restrict__ off, int n,
     return lo;
 }
 
-template <int EQ, int DIR>
-__global__ void __launch_bounds__(BLOCK) sweep2d_kernel(Step2D S, DevParams P)
+template <int EQ, int DIR, int L>
+__global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
 {
+    constexpr int NB = 64 * L;
     constexpr int M = NComp<EQ, 2>::M;
     const int inst = find_instance(S.tile_off[DIR], S.n_inst, blockIdx.x);
     const double dt = S.dt[inst];
@@ -112,7 +114,7 @@ __global__ void __launch_bounds__(BLOCK) sweep2d_kernel(Step2D S, DevParams P)
     const int tiles_s = (ns + CHUNK - 1) / CHUNK;
     const int tile = blockIdx.x - S.tile_off[DIR][inst];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
-    const int t = (tile / tiles_s) * LINES + wave;
+    const int t = (tile / tiles_s) * L + wave;
     if (t >= nt) return;
     const int s = (tile % tiles_s) * CHUNK + lane - 2;
     const bool live = s <= ns + 1;
@@ -124,7 +126,7 @@ __global__ void __launch_bounds__(BLOCK) sweep2d_kernel(Step2D S, DevParams P)
     // The stage-1 polynomials are parked in LDS for the node loop: a 256-lane
     // block of this kernel fills a CU's register file on its own, so the LDS
     // is free; the layout [coefficient][lane] keeps accesses conflict-free.
-    __shared__ double s_poly[2][M][5][BLOCK];
+    __shared__ double s_poly[2][M][5][NB];
     double Wc[M];
     bool full = P.weights == W_NONLINEAR;
     bool charpath;
@@ -203,8 +205,8 @@ __global__ void __launch_bounds__(BLOCK) sweep2d_kernel(Step2D S, DevParams P)
                 double pw[5], pv[5];
 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
-                    pw[k] = vp[((0 * M + c) * 5 + k) * BLOCK + threadIdx.x];
-                    pv[k] = vp[((1 * M + c) * 5 + k) * BLOCK + threadIdx.x];
+                    pw[k] = vp[((0 * M + c) * 5 + k) * NB + threadIdx.x];
+                    pv[k] = vp[((1 * M + c) * 5 + k) * NB + threadIdx.x];
                 }
                 const double A = deriv_at(pw, node[g], n, sct[n]);
                 const double B = deriv_at(pv, node[g], n, sct[n]);
@@ -322,21 +324,22 @@ __global__ void __launch_bounds__(BLOCK) sweep2d_kernel(Step2D S, DevParams P)
 // line through the cell in that direction, its normal components; the
 // network is the 1D one) and the cell takes the nonlinear weights if either
 // score reaches the threshold.  Both sweeps of the step read the flags.
-// Tiles as for the x-sweep: 4 rows x 60 cells, one wave per row, lane l on
+// Tiles as for the x-sweep: L rows x 60 cells, one wave per row, lane l on
 // cell c0 + l - 2 (every lane evaluates; lanes 2..61 store).
-__global__ void __launch_bounds__(BLOCK) gate2d_kernel(Step2D S, DevParams P)
+template <int L>
+__global__ void __launch_bounds__(64 * L) gate2d_kernel(Step2D S, DevParams P)
 {
     constexpr int M = 4;
     __shared__ u32x4 s_gate[GATE_LDS_WORDS];
     const int inst = find_instance(S.tile_off[0], S.n_inst, blockIdx.x);
     if (!(S.dt[inst] > 0.0)) return;              // the whole block: instance idle
-    gate_to_lds(S.gate, s_gate, threadIdx.x, BLOCK);
+    gate_to_lds(S.gate, s_gate, threadIdx.x, 64 * L);
     __syncthreads();
     const Inst2D d = S.inst[inst];
     const int tiles_s = (d.nx + CHUNK - 1) / CHUNK;
     const int tile = blockIdx.x - S.tile_off[0][inst];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
-    const int t = (tile / tiles_s) * LINES + wave;
+    const int t = (tile / tiles_s) * L + wave;
     if (t >= d.ny) return;                        // the whole wave: past the last row
     const int s = (tile % tiles_s) * CHUNK + lane - 2;
     const int sc = s < 0 ? 0 : (s >= d.nx ? d.nx - 1 : s);   // lanes off the row: any cell
@@ -471,9 +474,9 @@ __global__ void clear_parity2d_kernel(Step2D S)
 
 } // namespace
 
-int sweep2d_tiles(int n_sweep, int n_trans)
+int sweep2d_tiles(int n_sweep, int n_trans, int lines)
 {
-    return ((n_sweep + CHUNK - 1) / CHUNK) * ((n_trans + LINES - 1) / LINES);
+    return ((n_sweep + CHUNK - 1) / CHUNK) * ((n_trans + lines - 1) / lines);
 }
 
 hipError_t launch_speed2d(int eq, const Step2D &S, const DevParams &P, int use_parity,
@@ -484,20 +487,29 @@ hipError_t launch_speed2d(int eq, const Step2D &S, const DevParams &P, int use_p
     return hipGetLastError();
 }
 
+template <int L>
+static void sweeps2d(int eq, const Step2D &S, const DevParams &P, const int total_tiles[2],
+                     hipStream_t st)
+{
+    if (eq == EULER && P.weights == W_LEARNED)
+        gate2d_kernel<L><<<total_tiles[0], 64 * L, 0, st>>>(S, P);
+    if (eq == EULER) {
+        sweep2d_kernel<EULER, 0, L><<<total_tiles[0], 64 * L, 0, st>>>(S, P);
+        sweep2d_kernel<EULER, 1, L><<<total_tiles[1], 64 * L, 0, st>>>(S, P);
+    } else {
+        sweep2d_kernel<ADV, 0, L><<<total_tiles[0], 64 * L, 0, st>>>(S, P);
+        sweep2d_kernel<ADV, 1, L><<<total_tiles[1], 64 * L, 0, st>>>(S, P);
+    }
+}
+
 hipError_t launch_step2d(int eq, const Step2D &S, const DevParams &P, int fixed,
-                         const int total_tiles[2], hipStream_t st)
+                         const int total_tiles[2], int lines, hipStream_t st)
 {
     const int nb = (S.n_inst + 255) / 256;
     prepare2d_kernel<<<nb, 256, 0, st>>>(S, P, fixed);
-    if (eq == EULER && P.weights == W_LEARNED)
-        gate2d_kernel<<<total_tiles[0], BLOCK, 0, st>>>(S, P);
-    if (eq == EULER) {
-        sweep2d_kernel<EULER, 0><<<total_tiles[0], BLOCK, 0, st>>>(S, P);
-        sweep2d_kernel<EULER, 1><<<total_tiles[1], BLOCK, 0, st>>>(S, P);
-    } else {
-        sweep2d_kernel<ADV, 0><<<total_tiles[0], BLOCK, 0, st>>>(S, P);
-        sweep2d_kernel<ADV, 1><<<total_tiles[1], BLOCK, 0, st>>>(S, P);
-    }
+    if (lines == 1) sweeps2d<1>(eq, S, P, total_tiles, st);
+    else if (lines == 2) sweeps2d<2>(eq, S, P, total_tiles, st);
+    else sweeps2d<4>(eq, S, P, total_tiles, st);
     finish2d_kernel<<<nb, 256, 0, st>>>(S);
     return hipGetLastError();
 }

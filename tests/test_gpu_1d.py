@@ -190,3 +190,36 @@ def test_restart_from_checkpoint_is_bitwise():
     c.set_times(t)
     c.advance_to(1.0, max_steps=20)
     assert np.array_equal(c.get_state(0), ref)
+
+
+def test_tile_variants_and_autotuner():
+    """Every tile variant (2, 4, 8 waves per instance) gives the same result
+    bit for bit; the autotuner picks one and leaves state and times as they
+    were."""
+    insts = WL.riemann_batch_1d(count=40, seed=8, nmin=20, nmax=700)
+    meshes = [S.Mesh.line(d.n, d.x0, d.x1, S.BC_TRANSMISSIVE) for d in insts]
+    ref = None
+    for v in (0, 1, 2):
+        s = S.Solver(meshes, gparams(S.EULER))
+        assert s.get_tile() == 1
+        s.set_tile(v)
+        for i, d in enumerate(insts):
+            s.set_state(i, d.state())
+        steps = s.advance_to(0.05, raise_nonphysical=False)
+        got = [s.get_state(i) for i in range(len(insts))]
+        if ref is None:
+            ref = (steps, got)
+        else:
+            assert np.array_equal(steps, ref[0])
+            for a, b in zip(got, ref[1]):
+                assert np.array_equal(a, b)
+    before = [s.get_state(i) for i in range(len(insts))]
+    t0, k0 = s.times()
+    best, ms = s.autotune(steps=4)
+    assert best in (0, 1, 2) and s.get_tile() == best and min(ms) > 0
+    t1, k1 = s.times()
+    assert np.array_equal(t0, t1) and np.array_equal(k0, k1)
+    for i in range(len(insts)):
+        assert np.array_equal(s.get_state(i), before[i])
+    with pytest.raises(RuntimeError):
+        s.set_tile(3)

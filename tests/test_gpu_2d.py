@@ -218,3 +218,38 @@ def test_graph_replays_match_eager_launches(weights):
         a.state.mul_(1.0)
         torch.cuda.synchronize()
     assert ka.sum() > 0
+
+
+def test_tile_variants_and_autotuner():
+    """Every tile variant (1, 2, 4 lines of 60 cells) gives the same result
+    bit for bit, graphs on; the autotuner picks one and leaves state and times
+    as they were."""
+    sizes = [24, 70, 46]
+    insts = WL.four_quadrant_batch(count=3, seed=11)
+    meshes = [S.Mesh.rect(n, n, 0.0, 1.0, 0.0, 1.0, S.BC_TRANSMISSIVE, S.BC_TRANSMISSIVE)
+              for n in sizes]
+    ref = None
+    for v in (0, 1, 2):
+        s = S.Solver(meshes, gparams())
+        assert s.get_tile() == 2
+        s.set_tile(v)
+        for i, (n, d) in enumerate(zip(sizes, insts)):
+            s.set_state(i, WL.four_quadrant(n, d.quads))
+        steps = s.advance_to(0.03, raise_nonphysical=False)
+        got = [s.get_state(i) for i in range(len(sizes))]
+        if ref is None:
+            ref = (steps, got)
+        else:
+            assert np.array_equal(steps, ref[0])
+            for a, b in zip(got, ref[1]):
+                assert np.array_equal(a, b)
+    before = [s.get_state(i) for i in range(len(sizes))]
+    t0, k0 = s.times()
+    best, ms = s.autotune(steps=8)
+    assert best in (0, 1, 2) and s.get_tile() == best and min(ms) > 0
+    t1, k1 = s.times()
+    assert np.array_equal(t0, t1) and np.array_equal(k0, k1)
+    for i in range(len(sizes)):
+        assert np.array_equal(s.get_state(i), before[i])
+    # and it keeps stepping as before
+    s.advance_to(0.04, raise_nonphysical=False)
