@@ -98,7 +98,7 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, int t, floa
 
 hipError_t launch_loop1d(int eq, const Loop1D &L, const DevParams &P, int grid, int variant,
                          hipStream_t stream);
-int loop1d_max_blocks(int eq, int variant);
+int loop1d_max_blocks(int eq, int variant, bool learned);
 hipError_t launch_dt1d(int eq, const Inst1D *inst, int n_inst, const double *state,
                        const DevParams &P, double *dt_out, hipStream_t stream);
 

@@ -252,7 +252,7 @@ shw_status shw_create(const shw_mesh *meshes, int n_inst, const shw_params *para
         s = c->hip(hipMemcpyAsync(c->ws + c->lay.inst, i1.data(), i1.size() * sizeof(Inst1D),
                                   hipMemcpyHostToDevice, c->stream), "copy instances");
         c->variant = 1;
-        c->grid1d = loop1d_max_blocks(params->eq, c->variant);
+        c->grid1d = loop1d_max_blocks(params->eq, c->variant, params->weights == SHW_W_LEARNED);
     } else {
         s = c->hip(hipMemcpyAsync(c->ws + c->lay.inst, i2.data(), i2.size() * sizeof(Inst2D),
                                   hipMemcpyHostToDevice, c->stream), "copy instances");
@@ -563,7 +563,8 @@ shw_status shw_set_tile(shw_ctx *c, int variant)
         c->chunk_exec = nullptr;
     }
     c->variant = variant;
-    if (c->dim == 1) c->grid1d = loop1d_max_blocks(c->params.eq, variant);
+    if (c->dim == 1)
+        c->grid1d = loop1d_max_blocks(c->params.eq, variant, c->params.weights == SHW_W_LEARNED);
     return SHW_OK;
 }
 

@@ -60,7 +60,7 @@ __device__ __forceinline__ int flag_cell(int q, int n, int bc_lo, int bc_hi)
     return q;
 }
 
-template <int EQ, int NB>
+template <int EQ, int NB, bool LRN>
 __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__restrict__ src,
                                                double *__restrict__ dst, double dt,
                                                const DevParams &P,
@@ -85,8 +85,8 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
         load_cell<EQ, M>(src, n, jl + 1, d.bc_lo, d.bc_hi, Wp, Vp);
         bool full = P.weights == W_NONLINEAR;
         if (P.weights == W_GATED) full = flags[d.cell_off + s0] != 0;
-        if constexpr (EQ == EULER) {
-            if (P.weights == W_LEARNED) {
+        if constexpr (LRN) {
+            {
                 if (gate_since == 0) {
                     // the whole wave evaluates the network for its 64 cells;
                     // the owners keep the decision for the steps until the next
@@ -146,15 +146,18 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
     return bad;
 }
 
-template <int EQ, int NB>
-__global__ void __launch_bounds__(NB) loop1d_kernel(Loop1D Lp, DevParams P)
+// LRN: the learned-gate instantiation (Euler only); the others carry no gate
+// code, which keeps its matrix-core accumulators out of their register count.
+template <int EQ, int NB, bool LRN>
+__global__ void __launch_bounds__(NB)
+loop1d_kernel(Loop1D Lp, DevParams P)
 {
     constexpr int M = NComp<EQ, 1>::M;
     __shared__ int s_item;
     __shared__ double s_red[NB / WAVE];
     __shared__ u32x4 s_gate[EQ == EULER ? GATE_LDS_WORDS : 1];
     const int tid = threadIdx.x;
-    if (EQ == EULER && P.weights == W_LEARNED) {
+    if constexpr (LRN) {
         // the packed network, shared by the waves, transposed for the LDS
         gate_to_lds(Lp.gate, s_gate, tid, NB);
         __syncthreads();
@@ -207,7 +210,7 @@ __global__ void __launch_bounds__(NB) loop1d_kernel(Loop1D Lp, DevParams P)
             // steps of the instance; steps are separated by block barriers, so
             // the decisions one wave stores are seen by the other waves
             gate_since = (k == 0 || (st.steps + k) % Lp.gate_every == 0) ? 0 : gate_since + 1;
-            const bool bad = sweep_instance<EQ, NB>(d, A, B, dt, P, Lp.flags, s_gate,
+            const bool bad = sweep_instance<EQ, NB, LRN>(d, A, B, dt, P, Lp.flags, s_gate,
                                                     Lp.gate_logit_min, gate_since);
             const int any_bad = __syncthreads_or(bad);
             double *tmp = A; A = B; B = tmp;
@@ -267,19 +270,25 @@ template <int NB>
 static void launch_loop1d_nb(int eq, const Loop1D &L, const DevParams &P, int grid,
                              hipStream_t stream)
 {
-    if (eq == EULER) loop1d_kernel<EULER, NB><<<grid, NB, 0, stream>>>(L, P);
-    else if (eq == BURG) loop1d_kernel<BURG, NB><<<grid, NB, 0, stream>>>(L, P);
-    else loop1d_kernel<ADV, NB><<<grid, NB, 0, stream>>>(L, P);
+    if (eq == EULER && P.weights == W_LEARNED) loop1d_kernel<EULER, NB, true><<<grid, NB, 0, stream>>>(L, P);
+    else if (eq == EULER) loop1d_kernel<EULER, NB, false><<<grid, NB, 0, stream>>>(L, P);
+    else if (eq == BURG) loop1d_kernel<BURG, NB, false><<<grid, NB, 0, stream>>>(L, P);
+    else loop1d_kernel<ADV, NB, false><<<grid, NB, 0, stream>>>(L, P);
 }
 
 template <int NB>
-static int loop1d_per_cu(int eq)
+static int loop1d_per_cu(int eq, bool learned)
 {
     int per_cu = 0;
     hipError_t e;
-    if (eq == EULER) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop1d_kernel<EULER, NB>, NB, 0);
-    else if (eq == BURG) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop1d_kernel<BURG, NB>, NB, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop1d_kernel<ADV, NB>, NB, 0);
+    if (eq == EULER && learned)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop1d_kernel<EULER, NB, true>, NB, 0);
+    else if (eq == EULER)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop1d_kernel<EULER, NB, false>, NB, 0);
+    else if (eq == BURG)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop1d_kernel<BURG, NB, false>, NB, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop1d_kernel<ADV, NB, false>, NB, 0);
     return (e != hipSuccess || per_cu < 1) ? 1 : per_cu;
 }
 
@@ -294,11 +303,11 @@ hipError_t launch_loop1d(int eq, const Loop1D &L, const DevParams &P, int grid, 
     return hipGetLastError();
 }
 
-int loop1d_max_blocks(int eq, int variant)
+int loop1d_max_blocks(int eq, int variant, bool learned)
 {
     const int nb = loop1d_threads(variant);
-    const int per_cu = nb == 128 ? loop1d_per_cu<128>(eq)
-                                 : nb == 512 ? loop1d_per_cu<512>(eq) : loop1d_per_cu<256>(eq);
+    const int per_cu = nb == 128 ? loop1d_per_cu<128>(eq, learned)
+                       : nb == 512 ? loop1d_per_cu<512>(eq, learned) : loop1d_per_cu<256>(eq, learned);
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);

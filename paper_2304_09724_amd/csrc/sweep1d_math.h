@@ -141,28 +141,20 @@ SHW_HD void ck1d(R w[M][5][5], const DevParams &P)
             }
     } else {
         const double gm1 = P.gamma - 1.0;
-        R r[5][5], u[5][5], mu[5][5], p[5][5], ep[5][5], epu[5][5];
+        // velocity by series division (rho u = m), no reciprocal series
+        const R r00 = 1.0 / w[0][0][0];
+        R u[5][5], mu[5][5], p[5][5], ep[5][5], epu[5][5];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
 #pragma unroll
             for (int a = 0; a + k <= 4; ++a) {
-                if (a == 0 && k == 0) {
-                    r[0][0] = 1.0 / w[0][0][0];
-                } else {
-                    R s = 0.0;
-#pragma unroll
-                    for (int b = 0; b <= a; ++b)
-#pragma unroll
-                        for (int j = 0; j <= k; ++j)
-                            if (b + j > 0) s += w[0][b][j] * r[a - b][k - j];
-                    r[a][k] = -s * r[0][0];
-                }
-                R su = 0.0;
+                R su = w[1][a][k];
 #pragma unroll
                 for (int b = 0; b <= a; ++b)
 #pragma unroll
-                    for (int j = 0; j <= k; ++j) su += w[1][b][j] * r[a - b][k - j];
-                u[a][k] = su;
+                    for (int j = 0; j <= k; ++j)
+                        if (b + j > 0) su -= w[0][b][j] * u[a - b][k - j];
+                u[a][k] = su * r00;
                 R sm = 0.0;
 #pragma unroll
                 for (int b = 0; b <= a; ++b)
