@@ -65,7 +65,8 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
                                                double *__restrict__ dst, double dt,
                                                const DevParams &P,
                                                uint8_t *__restrict__ flags, const u32x4 *gate,
-                                               float gate_logit_min, int gate_since)
+                                               float gate_logit_min, int gate_since,
+                                               double *spd_out)
 {
     constexpr int M = NComp<EQ, 1>::M;
     const int lane = threadIdx.x % WAVE;
@@ -74,6 +75,7 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
     const int nchunk = (n + CHUNK - 1) / CHUNK;
     const double idx = 1.0 / d.dx, dt_dx = dt * idx;
     bool bad = false;
+    double spd = 0.0;       // largest wave speed of the new averages of this lane
     for (int ch = wave; ch < nchunk; ch += NB / WAVE) {
         const int j = ch * CHUNK + lane - 1;       // this lane's cell, -1..n+61
         const bool live = j <= n;
@@ -141,8 +143,12 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
                 dst[(M + c) * n + j] = Vnew[c];
             }
             bad |= bad_state<EQ>(Wnew, P);
+            spd = fmax(spd, wave_speed<EQ>(Wnew, P));
         }
     }
+    // the next step's CFL speed, one value per wave (a0.. of spd_out)
+    spd = wave_max(spd);
+    if (lane == 0) spd_out[wave] = spd;
     return bad;
 }
 
@@ -154,7 +160,10 @@ loop1d_kernel(Loop1D Lp, DevParams P)
 {
     constexpr int M = NComp<EQ, 1>::M;
     __shared__ int s_item;
-    __shared__ double s_red[NB / WAVE];
+    // per-wave CFL speeds, double-buffered by step: a sweep writes the speeds
+    // of the averages it produces into one half while the step size of the
+    // running step was read from the other
+    __shared__ double s_spd[2][NB / WAVE];
     __shared__ u32x4 s_gate[EQ == EULER ? GATE_LDS_WORDS : 1];
     const int tid = threadIdx.x;
     if constexpr (LRN) {
@@ -180,6 +189,7 @@ loop1d_kernel(Loop1D Lp, DevParams P)
         long long k = 0;
         int code = 0;
         int gate_since = 0;
+        int buf = 0;              // s_spd[buf]: speeds of the averages in A, once k > 0
         while (k < Lp.max_steps) {
             double dt;
             bool last = false;
@@ -188,21 +198,23 @@ loop1d_kernel(Loop1D Lp, DevParams P)
                 dt = dt_fix;
             } else {
                 if (!(st.t < T)) break;
-                // CFL step size from the averages at t_n (block max reduction)
-                double smax = 0.0;
-                for (int j = tid; j < d.n; j += NB) {
-                    double W[M];
+                if (k == 0) {
+                    // first step of the launch: a pass over the averages at t_n
+                    double smax = 0.0;
+                    for (int j = tid; j < d.n; j += NB) {
+                        double W[M];
 #pragma unroll
-                    for (int c = 0; c < M; ++c) W[c] = A[c * d.n + j];
-                    smax = fmax(smax, wave_speed<EQ>(W, P));
+                        for (int c = 0; c < M; ++c) W[c] = A[c * d.n + j];
+                        smax = fmax(smax, wave_speed<EQ>(W, P));
+                    }
+                    smax = wave_max(smax);
+                    if (tid % WAVE == 0) s_spd[buf][tid / WAVE] = smax;
+                    __syncthreads();
                 }
-                smax = wave_max(smax);
-                if (tid % WAVE == 0) s_red[tid / WAVE] = smax;
-                __syncthreads();
-                smax = s_red[0];
+                // CFL step size: block max of the per-wave speeds
+                double smax = s_spd[buf][0];
 #pragma unroll
-                for (int w = 1; w < NB / WAVE; ++w) smax = fmax(smax, s_red[w]);
-                __syncthreads();
+                for (int w = 1; w < NB / WAVE; ++w) smax = fmax(smax, s_spd[buf][w]);
                 dt = P.cfl * d.dx / smax;
                 if (dt >= T - st.t) { dt = T - st.t; last = true; }
             }
@@ -211,8 +223,13 @@ loop1d_kernel(Loop1D Lp, DevParams P)
             // the decisions one wave stores are seen by the other waves
             gate_since = (k == 0 || (st.steps + k) % Lp.gate_every == 0) ? 0 : gate_since + 1;
             const bool bad = sweep_instance<EQ, NB, LRN>(d, A, B, dt, P, Lp.flags, s_gate,
-                                                    Lp.gate_logit_min, gate_since);
+                                                         Lp.gate_logit_min, gate_since,
+                                                         s_spd[buf ^ 1]);
+            // a full barrier (with workgroup fences) orders the speeds in LDS and
+            // the gate's stored decisions for the next step
+            __syncthreads();
             const int any_bad = __syncthreads_or(bad);
+            buf ^= 1;
             double *tmp = A; A = B; B = tmp;
             ++k;
             st.t = last ? T : st.t + dt;
