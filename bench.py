@@ -183,10 +183,13 @@ def gated_leg(S, insts, states, meshes, init, args, plain_value, plain):
 def gated_2d_leg(S, params, threshold=0.05, steps=40):
     """The learned gate on 2D Euler: the shock/sine problem (Mach-3 shock into
     rho = 1 + 0.2 sin 5x sin 3y on (-5,5) x (0,2pi/3); 2048 x 512 cells, a
-    quarter of the 4096 x 1024 shape, whose exact initial averages take
-    minutes on the host), a window of `steps` CFL steps from t = 0, plain and
-    gated: throughput and the gated density's departure from the plain one."""
+    quarter of the 4096 x 1024 shape), a window of `steps` CFL steps from
+    t = 0 with autotuned tiles, plain and gated: throughput, the plain run
+    against the FP64 roofline (HIP events on the solver's stream around the
+    whole advance, which holds the sweeps and the small time-loop kernels),
+    and the gated density's departure from the plain one."""
     import torch
+    from paper_2304_09724_amd import flopcount
     from paper_2304_09724_amd import workloads as WL
     nx, ny = 2048, 512
     m = [S.Mesh.rect(nx, ny, -5.0, 5.0, 0.0, 2 * np.pi / 3, S.BC_TRANSMISSIVE, S.BC_PERIODIC)]
@@ -202,24 +205,58 @@ def gated_2d_leg(S, params, threshold=0.05, steps=40):
             s.gate_load(params)
         s.set_state(0, st)
         init = s.state.clone()
+        tile, _ = s.autotune(steps=8)
         s.advance_to(1e9, max_steps=2)
         s.state.copy_(init)
         s.set_times(0.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        e0.record(s.stream)
         k = s.advance_to(1e9, max_steps=steps)
+        e1.record(s.stream)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        out[name] = nx * ny * int(k[0]) / el
+        cu = nx * ny * int(k[0])
+        out[name] = cu / el
+        out[name + "_tile_lines"] = [1, 2, 4][tile]
         res[name] = s.get_state(0)[0, 0]
-        if name == "gated":
+        if name == "plain":
+            ms = e0.elapsed_time(e1)
+            flops = flopcount.euler2d_cell_update(True)["flops"]
+            tf = flops * cu / (ms * 1e-3) / 1e12
+            out["roofline_plain"] = {
+                "bound": "alu", "achieved": round(tf, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(tf / FP64_VECTOR_PEAK_TFLOPS, 4),
+                "flops_per_cell_update": flops, "ms": round(ms, 3),
+                "hbm_algorithmic_GBs": round(256 * cu / (ms * 1e-3) / 1e9, 1)}
+        else:
             out["cells_gated_nonlinear_last_step"] = float(s.get_flags(0).mean())
         del s
     out["speedup"] = out["gated"] / out["plain"]
     R = float(res["plain"].max() - res["plain"].min())
     out["max_abs_density_diff_over_range"] = float(np.abs(res["gated"] - res["plain"]).max() / R)
     out["l1_density_diff"] = float(np.abs(res["gated"] - res["plain"]).mean())
+    out["cpu_oracle_2d"] = cpu_baseline_2d()
     return out
+
+
+def cpu_baseline_2d(n=48, steps=4):
+    """The CPU oracle's 2D step on a 48 x 48 piece of the same problem, a few
+    steps (its own OpenMP over rows)."""
+    import oracle as O
+    from paper_2304_09724_amd import workloads as WL
+    st = WL.shock_sine_2d(10 * n // 2, n)[:, :, :, :n].copy()
+    cfg = O.Config(eq=O.EULER, bc=(O.BC_PERIODIC,) * 4)
+    dx, dy = 10.0 / (10 * n // 2), (2 * np.pi / 3) / n
+    dt = O.dt2d(cfg, st, dx, dy, 0.9)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st, bad = O.step2d(cfg, st, dx, dy, dt)
+    wall = time.perf_counter() - t0
+    return {"value": n * n * steps / wall, "unit": "cell-updates/s", "kind": "oracle",
+            "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count())), "sample": f"{n}x{n} cells of the 2D shock/sine field, "
+                                             f"{steps} steps, {wall:.1f} s wall"}
 
 
 def main():
@@ -229,6 +266,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gate", action="store_true")
+    ap.add_argument("--only-2d", action="store_true",
+                    help="train the gate and run only the 2D leg (plain and gated)")
     ap.add_argument("--copy-check", type=int, default=0, metavar="BYTES",
                     help="after the timed steps, copy a device buffer of this many bytes once "
                          "(a plain copy kernel of known traffic, to scale HBM counters by)")
@@ -238,6 +277,14 @@ def main():
                                    "sharded by instance across GPUs with no communication "
                                    "(see the multi-GPU design notes)", "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.only_2d:
+        import paper_2304_09724_amd as S
+        from paper_2304_09724_amd import gate as GT
+        X, y = GT.collect(GT.training_problems(), times=[0.0, 0.02, 0.06, 0.1, 0.14])
+        params, _ = GT.train(X, y)
+        print(json.dumps({"gated_2d": gated_2d_leg(S, params)}), flush=True)
+        return
 
     import torch
     import paper_2304_09724_amd as S

@@ -318,7 +318,6 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
     }
 }
 
-// max over the cells of (|u|+c)/dx + (|v|+c)/dy, one block per instance
 // The learned gate of one 2D Euler step: for every cell of the instances
 // that step, the network scores the cell along x and along y (features of the
 // line through the cell in that direction, its normal components; the
@@ -369,18 +368,30 @@ __global__ void __launch_bounds__(64 * L) gate2d_kernel(Step2D S, DevParams P)
             (uint8_t)(fmaxf(z[0], z[1]) >= S.gate_logit_min);
 }
 
+// max over the cells of (|u|+c)/dx + (|v|+c)/dy: SPEED_SPLIT blocks per
+// instance (grid SPEED_SPLIT x instances), each over every SPEED_SPLIT-th
+// stretch of BLOCK cells, combined by an atomic max into the cleared slot
+constexpr int SPEED_SPLIT = 64;
+
+__global__ void clear_smax2d_kernel(Step2D S)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < S.n_inst) S.smax[i] = 0.0;
+}
+
 template <int EQ>
 __global__ void __launch_bounds__(BLOCK) speed2d_kernel(Step2D S, DevParams P, int use_parity)
 {
     constexpr int M = NComp<EQ, 2>::M;
     __shared__ double red[LINES];
-    const int inst = blockIdx.x;
+    const int inst = blockIdx.y;
     const Inst2D d = S.inst[inst];
     const double *src = ((use_parity && S.parity[inst]) ? S.alt : S.state) + d.off;
     const long long plane = (long long)d.nx * d.ny;
     double m = 0.0;
     bool bad = false;
-    for (long long o = threadIdx.x; o < plane; o += BLOCK) {
+    for (long long o = (long long)blockIdx.x * BLOCK + threadIdx.x; o < plane;
+         o += (long long)SPEED_SPLIT * BLOCK) {
         double W[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) W[c] = src[c * plane + o];
@@ -407,8 +418,10 @@ __global__ void __launch_bounds__(BLOCK) speed2d_kernel(Step2D S, DevParams P, i
     if (threadIdx.x == 0) {
         double r = red[0];
         for (int w = 1; w < LINES; ++w) r = fmax(r, red[w]);
-        S.smax[inst] = r;
-        if (any_bad) S.bad[inst] = 1;
+        // positive doubles order like their bit patterns
+        atomicMax(reinterpret_cast<unsigned long long *>(&S.smax[inst]),
+                  (unsigned long long)__double_as_longlong(r));
+        if (any_bad) atomicOr(&S.bad[inst], 1);
     }
 }
 
@@ -482,8 +495,10 @@ int sweep2d_tiles(int n_sweep, int n_trans, int lines)
 hipError_t launch_speed2d(int eq, const Step2D &S, const DevParams &P, int use_parity,
                           hipStream_t st)
 {
-    if (eq == EULER) speed2d_kernel<EULER><<<S.n_inst, BLOCK, 0, st>>>(S, P, use_parity);
-    else speed2d_kernel<ADV><<<S.n_inst, BLOCK, 0, st>>>(S, P, use_parity);
+    clear_smax2d_kernel<<<(S.n_inst + 255) / 256, 256, 0, st>>>(S);
+    const dim3 grid(SPEED_SPLIT, S.n_inst);
+    if (eq == EULER) speed2d_kernel<EULER><<<grid, BLOCK, 0, st>>>(S, P, use_parity);
+    else speed2d_kernel<ADV><<<grid, BLOCK, 0, st>>>(S, P, use_parity);
     return hipGetLastError();
 }
 
