@@ -328,7 +328,9 @@ def main():
         steps = solver.advance_to(T, raise_nonphysical=False)
         ev[k][1].record(stream)
         cell_updates.append(int((ncell * steps).sum()))
-        log(f"step {k}: {cell_updates[-1]} cell-updates")
+        ev[k][1].synchronize()
+        log(f"step {k}: {cell_updates[-1]} cell-updates, "
+            f"{ev[k][0].elapsed_time(ev[k][1]):.2f} ms")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
