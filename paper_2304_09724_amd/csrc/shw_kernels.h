@@ -54,6 +54,8 @@ struct Loop1D {
     const GateLane *gate;      // packed network (LEARNED mode)
     float gate_logit_min;      // cells with logit >= this take the full reconstruction
     int gate_every;            // LEARNED: evaluate the network every this many steps
+    double share;              // cell-updates per workgroup if the launch's estimated work
+                               // were spread evenly; > 0 turns on work-based wave priority
 };
 
 // Launch parameters of one 2D step over a batch (all pointers device-side).

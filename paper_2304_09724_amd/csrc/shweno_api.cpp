@@ -121,6 +121,8 @@ struct shw_ctx {
     int tiles2d[N_TILE_VARIANTS][2] = {};
     bool gate_loaded = false;
     int bad_instance = -1;
+    std::vector<int> order_host;        // 1D: the last launch's instance order (kept
+                                        // alive for its asynchronous upload)
     std::string msg;
     // 2D: a chunk of steps captured once as a HIP graph and replayed
     bool use_graphs = true;
@@ -640,8 +642,44 @@ shw_status shw_set_graphs(shw_ctx *c, int enable)
     return SHW_OK;
 }
 
+// 1D schedule of a CFL launch towards T: each instance's work is estimated as
+// its cells times the steps its current CFL step size needs to reach T (at
+// most max_steps); the persistent workgroups take instances heaviest first,
+// and share is the work per workgroup if it were spread evenly (the kernel's
+// wave priorities are set against it).
+static shw_status schedule1d(shw_ctx *c, const double *T, long long max_steps, int grid,
+                             double &share)
+{
+    const int n = c->n_inst;
+    double *d_dt = c->at<double>(c->lay.dt);
+    shw_status s = c->hip(launch_dt1d(c->params.eq, c->at<Inst1D>(c->lay.inst), n, c->state,
+                                      c->dp, d_dt, c->stream), "schedule dt");
+    std::vector<double> dt(n);
+    if (s == SHW_OK)
+        s = c->hip(hipMemcpyAsync(dt.data(), d_dt, n * sizeof(double), hipMemcpyDeviceToHost,
+                                  c->stream), "schedule dt copy");
+    std::vector<InstState> ist;
+    if (s == SHW_OK) s = read_ist(c, ist);
+    if (s != SHW_OK) return s;
+    std::vector<double> work(n, 0.0);
+    double total = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (ist[i].code != 0 || !(dt[i] > 0.0) || !(T[i] > ist[i].t)) continue;
+        const double steps = std::min((double)max_steps, std::ceil((T[i] - ist[i].t) / dt[i]));
+        work[i] = (double)c->meshes[i].nx * steps;
+        total += work[i];
+    }
+    c->order_host.resize(n);
+    std::iota(c->order_host.begin(), c->order_host.end(), 0);
+    std::stable_sort(c->order_host.begin(), c->order_host.end(),
+                     [&](int a, int b) { return work[a] > work[b]; });
+    share = total / std::max(grid, 1);
+    return c->hip(hipMemcpyAsync(c->ws + c->lay.order, c->order_host.data(), n * sizeof(int),
+                                 hipMemcpyHostToDevice, c->stream), "schedule order");
+}
+
 // CFL steps towards the end times T (host array) with the current tile
-// variant; asynchronous except for the 2D chunk polls.
+// variant; asynchronous except for the 2D chunk polls and the 1D schedule.
 static shw_status run_to(shw_ctx *c, const double *T, long long max_steps)
 {
     double *d_T = c->at<double>(c->lay.t_end);
@@ -654,6 +692,8 @@ static shw_status run_to(shw_ctx *c, const double *T, long long max_steps)
     L.t_end = d_T;
     L.max_steps = max_steps;
     int grid = std::min(c->grid1d, c->n_inst);
+    s = schedule1d(c, T, max_steps, grid, L.share);
+    if (s != SHW_OK) return s;
     return c->hip(launch_loop1d(c->params.eq, L, c->dp, grid, c->variant, c->stream), "advance");
 }
 

@@ -154,6 +154,24 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
 
 // LRN: the learned-gate instantiation (Euler only); the others carry no gate
 // code, which keeps its matrix-core accumulators out of their register count.
+// Two persistent workgroups share a compute unit, and each SIMD issues from
+// its oldest ready wave first: left to that order, an instance that landed on
+// the younger workgroup runs at a fraction of its speed for as long as the
+// older one keeps finding work, and a heavy one then ends the launch late.
+// Each step the waves take a priority from their instance's remaining work
+// (cells x steps left) against the launch's even share per workgroup, so the
+// instances likely to finish last are issued first.
+__device__ inline void work_priority(double work, double share)
+{
+    const int p = work >= 0.5 * share ? 3 : work >= 0.25 * share ? 2 : work >= 0.125 * share ? 1 : 0;
+    switch (__builtin_amdgcn_readfirstlane(p)) {
+    case 3: __builtin_amdgcn_s_setprio(3); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    default: __builtin_amdgcn_s_setprio(0); break;
+    }
+}
+
 template <int EQ, int NB, bool LRN>
 __global__ void __launch_bounds__(NB)
 loop1d_kernel(Loop1D Lp, DevParams P)
@@ -217,6 +235,9 @@ loop1d_kernel(Loop1D Lp, DevParams P)
                 for (int w = 1; w < NB / WAVE; ++w) smax = fmax(smax, s_spd[buf][w]);
                 dt = P.cfl * d.dx / smax;
                 if (dt >= T - st.t) { dt = T - st.t; last = true; }
+                if (Lp.share > 0.0)
+                    work_priority(d.n * fmin((double)(Lp.max_steps - k), ceil((T - st.t) / dt)),
+                                  Lp.share);
             }
             // the gate runs at the first step of a launch and every gate_every
             // steps of the instance; steps are separated by block barriers, so
