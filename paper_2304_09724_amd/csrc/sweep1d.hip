@@ -172,8 +172,10 @@ __device__ inline void work_priority(double work, double share)
     }
 }
 
+// Two waves per SIMD (at most 256 registers a lane) is the occupancy the
+// kernel is written for: one wave alone cannot hide its FP64 latencies.
 template <int EQ, int NB, bool LRN>
-__global__ void __launch_bounds__(NB)
+__global__ void __launch_bounds__(NB) __attribute__((amdgpu_waves_per_eu(2)))
 loop1d_kernel(Loop1D Lp, DevParams P)
 {
     constexpr int M = NComp<EQ, 1>::M;
@@ -192,7 +194,8 @@ loop1d_kernel(Loop1D Lp, DevParams P)
     for (;;) {
         if (tid == 0) s_item = atomicAdd(Lp.queue, 1);
         __syncthreads();
-        const int item = s_item;
+        // the same word for every lane: a scalar, and so is what is indexed by it
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (item >= Lp.n_inst) break;
         const int i = Lp.order[item];
