@@ -95,6 +95,26 @@ def burgers_sine(n: int, x0=0.0, x1=2.0):
     return np.ascontiguousarray(np.stack([Wbar[None], V[None]]))
 
 
+def burgers_sine_exact(n: int, t: float, x0=0.0, x1=2.0):
+    """Exact cell averages at time t < 1/pi (before the shock forms) of
+    Burgers' equation from W0 = 0.5 + sin(pi x): the value at x is the root of
+    w = 0.5 + sin(pi (x - w t)) (the characteristic through x), found by
+    Newton's iteration (its derivative 1 + pi t cos(.) stays positive), then
+    averaged by Gauss-Legendre quadrature."""
+    assert 0.0 <= t < 1.0 / np.pi
+
+    def point(x):
+        w = 0.5 + np.sin(np.pi * x)
+        for _ in range(60):
+            ph = np.pi * (x - w * t)
+            step = (w - 0.5 - np.sin(ph)) / (1.0 + np.pi * t * np.cos(ph))
+            w = w - step
+            if np.abs(step).max() < 1e-16:
+                break
+        return w[None]
+    return averages_1d(point, x0, x1, n)[0, 0]
+
+
 def density_wave_1d(n: int, t: float = 0.0, gamma=GAMMA, x0=0.0, x1=2.0, u=1.0, amp=0.2,
                     k=1):
     """rho = 1 + amp sin(k pi (x - u t)), velocity u, p = 1 on periodic (0, 2)

@@ -82,3 +82,15 @@ def test_density_wave_2d_exact_average_matches_quadrature():
         rho = WL.density_wave_2d(n, t=0.37)[0, 0]
         np.testing.assert_allclose(WL.density_wave_2d_exact_rho(n, t=0.37), rho, rtol=0,
                                    atol=1e-14)
+
+
+def test_burgers_exact_averages():
+    """At t = 0 the exact averages equal the closed-form initial ones; later,
+    on the periodic domain, they keep the initial mean (conservation) and the
+    initial range (the solution is constant along characteristics)."""
+    n = 64
+    np.testing.assert_allclose(WL.burgers_sine_exact(n, 0.0), WL.burgers_sine(n)[0, 0],
+                               rtol=0, atol=1e-14)
+    w = WL.burgers_sine_exact(n, 0.25)
+    assert abs(w.mean() - 0.5) < 1e-14
+    assert w.min() >= -0.5 - 1e-12 and w.max() <= 1.5 + 1e-12
