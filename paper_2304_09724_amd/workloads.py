@@ -168,6 +168,42 @@ def riemann_1d(n: int, left, right, x0=0.0, x1=1.0, xd=0.5, gamma=GAMMA):
     return np.ascontiguousarray(np.stack([Wbar, V]))
 
 
+def piecewise_1d(n: int, states, breaks, x0, x1, gamma=GAMMA):
+    """Piecewise-constant Euler data: states[k] = (rho, u, p) on the k-th
+    interval between x0, the sorted breaks and x1.  Averages by covered
+    length; the derivative average of a cell is the sum of the jumps strictly
+    inside it over dx (a jump on a cell edge contributes nothing)."""
+    e = np.linspace(x0, x1, n + 1)
+    dx = (x1 - x0) / n
+    Ws = [prim_to_cons(*s, gamma=gamma) for s in states]
+    bounds = [x0, *breaks, x1]
+    Wbar = np.zeros((3, n))
+    for W, a, b in zip(Ws, bounds[:-1], bounds[1:]):
+        share = np.clip((np.minimum(e[1:], b) - np.maximum(e[:-1], a)) / dx, 0.0, 1.0)
+        share[(e[:-1] >= a) & (e[1:] <= b)] = 1.0          # whole cells exactly
+        Wbar += W[:, None] * share
+    V = np.zeros_like(Wbar)
+    for k, xb in enumerate(breaks):
+        inside = (e[:-1] < xb) & (e[1:] > xb)
+        V[:, inside] += ((Ws[k + 1] - Ws[k]) / dx)[:, None]
+    return np.ascontiguousarray(np.stack([Wbar, V]))
+
+
+def lax_tube(n: int, gamma=GAMMA):
+    """Lax's shock tube (sec. 5): (0.445, 0.698, 3.528) for x < 0 and
+    (0.5, 0, 0.571) for x > 0 on (-5, 5); inflow/outflow (transmissive) ends,
+    T = 1.3."""
+    return piecewise_1d(n, [(0.445, 0.698, 3.528), (0.5, 0.0, 0.571)], [0.0], -5.0, 5.0, gamma)
+
+
+def blast_waves(n: int, gamma=GAMMA):
+    """Interacting blast waves of Woodward and Colella (sec. 5): rho = 1, u = 0
+    and p = 1000 on [0, 0.1), 0.01 on [0.1, 0.9), 100 on [0.9, 1]; reflective
+    walls, T = 0.038."""
+    return piecewise_1d(n, [(1.0, 0.0, 1000.0), (1.0, 0.0, 0.01), (1.0, 0.0, 100.0)],
+                        [0.1, 0.9], 0.0, 1.0, gamma)
+
+
 # ---------------------------------------------------------------------------
 # 2D
 # ---------------------------------------------------------------------------

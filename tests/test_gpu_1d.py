@@ -115,6 +115,38 @@ def test_burgers_full_run():
     assert rel_err(g, o) < TOL
 
 
+def test_lax_tube_full_run():
+    """Lax's shock tube as the paper runs it (sec. 5): 200 cells on (-5, 5),
+    transmissive ends, T = 1.3 (138 CFL steps)."""
+    n = 200
+    st = WL.lax_tube(n)
+    _, (g,), steps = run_gpu([S.Mesh.line(n, -5.0, 5.0, S.BC_TRANSMISSIVE)], gparams(S.EULER),
+                             [st], 1.3)
+    o, t, osteps, bad = O.advance1d(ocfg(O.EULER, O.BC_TRANSMISSIVE), st, 10.0 / n, 0.9, 1.3)
+    assert not bad and steps[0] == osteps
+    assert rel_err(g, o) < TOL
+
+
+def test_blast_waves_full_runs():
+    """The interacting blast waves (sec. 5), reflective walls, T = 0.038, in
+    one batch: at 400 cells the whole run (705 steps) against the oracle's; at
+    200 and 800 cells the unlimited scheme meets a non-physical state, and the
+    GPU stops those instances at the oracle's step while the others run on."""
+    ns = [200, 400, 800]
+    s = S.Solver([S.Mesh.line(n, 0.0, 1.0, S.BC_REFLECTIVE) for n in ns], gparams(S.EULER))
+    for i, n in enumerate(ns):
+        s.set_state(i, WL.blast_waves(n))
+    steps = s.advance_to(np.full(len(ns), 0.038), raise_nonphysical=False)
+    codes = s.instance_status()
+    cfg = ocfg(O.EULER, O.BC_REFLECTIVE)
+    with cf.ThreadPoolExecutor(3) as ex:
+        res = list(ex.map(lambda n: O.advance1d(cfg, WL.blast_waves(n), 1.0 / n, 0.9, 0.038), ns))
+    assert [bool(r[3]) for r in res] == [True, False, True]
+    for i, (o, t, osteps, bad) in enumerate(res):
+        assert (codes[i] != 0) == bad and steps[i] == osteps, (ns[i], steps[i], osteps)
+    assert rel_err(s.get_state(1), res[1][0]) < TOL
+
+
 def test_compute_dt_matches_oracle():
     insts = WL.riemann_batch_1d(count=6, nmin=40, nmax=200)
     s = S.Solver([S.Mesh.line(d.n, d.x0, d.x1, S.BC_TRANSMISSIVE) for d in insts], gparams(S.EULER))

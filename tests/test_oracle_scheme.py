@@ -320,6 +320,19 @@ def test_riemann_problem_converges_to_exact_solution(left, right):
     assert e[1] < 0.75 * e[0] and e[2] < 0.75 * e[1], e
 
 
+def test_blast_waves_conserve_at_reflective_walls():
+    """The interacting blast waves (sec. 5) at 400 cells to T = 0.038 with
+    reflective walls: the run stays physical, and mass and energy, whose wall
+    fluxes vanish, are conserved to rounding."""
+    cfg = O.Config(eq=O.EULER, bc=(O.BC_REFLECTIVE,) * 4)
+    st = WL.blast_waves(400)
+    s, t, steps, bad = O.advance1d(cfg, st, 1.0 / 400, 0.9, 0.038)
+    assert not bad and t == 0.038
+    for c in (0, 2):
+        assert abs(s[0, c].sum() - st[0, c].sum()) <= 1e-14 * st[0, c].sum()
+    assert s[0, 0].min() > 0.1 and s[0, 0].max() < 7.0
+
+
 def test_transmissive_boundary_keeps_constant_state():
     cfg = O.Config(eq=O.EULER, bc=(O.BC_TRANSMISSIVE,) * 4)
     W = WL.prim_to_cons(np.full(20, 1.3), np.full(20, 0.4), np.full(20, 0.8))

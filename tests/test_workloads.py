@@ -94,3 +94,24 @@ def test_burgers_exact_averages():
     w = WL.burgers_sine_exact(n, 0.25)
     assert abs(w.mean() - 0.5) < 1e-14
     assert w.min() >= -0.5 - 1e-12 and w.max() <= 1.5 + 1e-12
+
+
+def test_piecewise_data_matches_the_two_state_form():
+    """One break: the piecewise form equals the two-state Riemann form, with the
+    jump inside a cell (n = 25, up to rounding of the split cell's shares) and
+    on a cell edge (n = 20)."""
+    L, R = (0.445, 0.698, 3.528), (0.5, 0.0, 0.571)
+    for n in (20, 25):
+        np.testing.assert_allclose(WL.lax_tube(n),
+                                   WL.riemann_1d(n, L, R, x0=-5.0, x1=5.0, xd=0.0),
+                                   rtol=1e-15, atol=1e-14)
+
+
+def test_blast_wave_data():
+    st = WL.blast_waves(400)                       # breaks on cell edges
+    p = (0.4 * st[0, 2])                           # u = 0: p = (gamma - 1) E
+    assert np.allclose(p[:40], 1000.0) and np.allclose(p[40:360], 0.01)
+    assert np.allclose(p[360:], 100.0) and np.abs(st[1]).max() == 0.0
+    st = WL.blast_waves(25)                        # 0.1 inside cell 2, 0.9 inside cell 22
+    assert 0.4 * st[0, 2, 2] == pytest.approx(0.5 * 1000.0 + 0.5 * 0.01)
+    assert st[1, 2, 2] == pytest.approx((0.01 - 1000.0) / 0.4 / 0.04)
