@@ -46,7 +46,7 @@ class _Cfg(ctypes.Structure):
                 ("weights", ctypes.c_int), ("bc", ctypes.c_int * 4),
                 ("gamma", ctypes.c_double), ("adv_a", ctypes.c_double),
                 ("adv_b", ctypes.c_double), ("eps", ctypes.c_double),
-                ("lin_w", ctypes.c_double * 3)]
+                ("lin_w", ctypes.c_double * 3), ("positivity", ctypes.c_int)]
 
 
 @dataclass
@@ -63,6 +63,7 @@ class Config:
     adv_b: float = 0.0
     eps: float = 1e-6
     lin_w: tuple = (0.994, 0.003, 0.003)
+    positivity: bool = False        # 1D Euler safeguard (not in the paper)
 
     def c(self) -> _Cfg:
         s = _Cfg()
@@ -72,6 +73,7 @@ class Config:
         s.gamma, s.adv_a, s.adv_b, s.eps = self.gamma, self.adv_a, self.adv_b, self.eps
         for k in range(3):
             s.lin_w[k] = self.lin_w[k]
+        s.positivity = int(self.positivity)
         return s
 
 
@@ -96,6 +98,7 @@ def lib():
         L.orc_recon_scalar.argtypes = [P, ctypes.c_int, _D, _D, _D]
         L.orc_euler_eigen.argtypes = [ctypes.c_double, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D]
         L.orc_hllc_state.argtypes = [ctypes.c_double, ctypes.c_int, _D, _D, _D]
+        L.orc_hlle.argtypes = [ctypes.c_double, ctypes.c_int, _D, _D, _D, _D]
         L.orc_euler_flux_x.argtypes = [ctypes.c_double, ctypes.c_int, _D, _D]
         L.orc_exact_riemann.argtypes = [ctypes.c_double] * 7 + [ctypes.c_double, _D]
         L.orc_exact_riemann.restype = ctypes.c_double
@@ -196,6 +199,15 @@ def hllc_state(gamma, WL, WR) -> np.ndarray:
     out = np.zeros(WL.size)
     lib().orc_hllc_state(gamma, 1 if WL.size == 3 else 2, _p(WL), _p(WR), _p(out))
     return out
+
+
+def hlle(gamma, WL, WR):
+    """HLLE flux and state at x/t = 0 (the positivity safeguard's first-order
+    face; not part of the paper's scheme)."""
+    WL, WR = _f64(WL), _f64(WR)
+    F, Ws = np.zeros(WL.size), np.zeros(WL.size)
+    lib().orc_hlle(gamma, 1 if WL.size == 3 else 2, _p(WL), _p(WR), _p(F), _p(Ws))
+    return F, Ws
 
 
 def exact_riemann(gamma, left, right, s):

@@ -118,6 +118,48 @@ void orc_hllc_state(double gamma, int dim, const double *WL, const double *WR,
     Wstar[m - 1] = f * (EK / rk + (Ss - uk) * (Ss + pk / (rk * (SK - uk))));
 }
 
+/* HLLE flux and state at x/t = 0 in the normal direction x (not part of the
+ * paper's scheme: the first-order flux of the positivity safeguard).  Harten,
+ * Lax and van Leer's single intermediate state between wave-speed bounds S_L,
+ * S_R from Einfeldt (SIAM J. Numer. Anal. 25, 1988): the smaller and larger of
+ * the two sides' acoustic speeds and of the Roe-averaged ones.  Between the
+ * bounds, the state is the one the integral form of the conservation law
+ * gives over the fan, and the flux the one consistent with it. */
+void orc_hlle(double gamma, int dim, const double *WL, const double *WR, double *F,
+              double *Wstar)
+{
+    const int m = dim == 1 ? 3 : 4;
+    double rl, ul, vl, pl, rr, ur, vr, pr, FL[4], FR[4];
+    euler_prim(gamma, dim, WL, &rl, &ul, &vl, &pl);
+    euler_prim(gamma, dim, WR, &rr, &ur, &vr, &pr);
+    orc_euler_flux_x(gamma, dim, WL, FL);
+    orc_euler_flux_x(gamma, dim, WR, FR);
+    double cl = sqrt(gamma * pl / rl), cr = sqrt(gamma * pr / rr);
+    /* Roe averages: weights sqrt(rho), enthalpy H = (E + p) / rho */
+    double sl = sqrt(rl), sr = sqrt(rr);
+    double hl = (WL[m - 1] + pl) / rl, hr = (WR[m - 1] + pr) / rr;
+    double ut = (sl * ul + sr * ur) / (sl + sr);
+    double vt = (sl * vl + sr * vr) / (sl + sr);
+    double ht = (sl * hl + sr * hr) / (sl + sr);
+    double ct = sqrt((gamma - 1.0) * (ht - 0.5 * (ut * ut + vt * vt)));
+    double SL = fmin(ul - cl, ut - ct);
+    double SR = fmax(ur + cr, ut + ct);
+    if (0.0 <= SL) {
+        memcpy(F, FL, m * sizeof(double));
+        memcpy(Wstar, WL, m * sizeof(double));
+        return;
+    }
+    if (SR <= 0.0) {
+        memcpy(F, FR, m * sizeof(double));
+        memcpy(Wstar, WR, m * sizeof(double));
+        return;
+    }
+    for (int c = 0; c < m; ++c) {
+        F[c] = (SR * FL[c] - SL * FR[c] + SL * SR * (WR[c] - WL[c])) / (SR - SL);
+        Wstar[c] = (SR * WR[c] - SL * WL[c] - (FR[c] - FL[c])) / (SR - SL);
+    }
+}
+
 /* ---- exact Riemann solver (Newton on the star-pressure equation) -------- */
 
 static void pressure_fn(double g, double p, double rk, double pk, double ck,

@@ -47,6 +47,8 @@ typedef struct {
     double adv_b;      /* advection speed in y */
     double eps;        /* regulariser of the nonlinear weights */
     double lin_w[3];   /* linear weights: quartic, left linear, right linear */
+    int positivity;    /* 1D Euler: 1 = the positivity safeguard of orc_step1d
+                          (an addition, not in the paper; 0 = the paper's scheme) */
 } orc_cfg;
 
 /* number of conservative components of an equation in dimension dim */
@@ -85,6 +87,11 @@ void orc_euler_eigen(double gamma, int dim, int dir, const double *W,
 void orc_hllc_state(double gamma, int dim, const double *WL, const double *WR,
                     double *Wstar);
 
+/* HLLE (Einfeldt's wave-speed bounds): flux F and state Wstar at x/t = 0
+ * (Euler, normal direction x).  Used only by the positivity safeguard. */
+void orc_hlle(double gamma, int dim, const double *WL, const double *WR, double *F,
+              double *Wstar);
+
 /* Exact Riemann solution of the 1D Euler equations sampled at x/t = s;
  * out = (rho, u, p).  Returns the star pressure. */
 double orc_exact_riemann(double gamma, double rl, double ul, double pl,
@@ -107,7 +114,10 @@ double orc_dt2d(const orc_cfg *cfg, int nx, int ny, double dx, double dy,
 
 /* One step of size dt.  flags (may be NULL unless cfg->weights is GATED):
  * one byte per cell, non-zero = full nonlinear reconstruction.  Returns 0,
- * or 1 if the new state has a non-finite value, rho<=0 or p<=0. */
+ * or 1 if the new state has a non-finite value, rho<=0 or p<=0.
+ * With cfg->positivity (1D Euler), the faces of cells whose update would be
+ * non-physical take the first-order HLLE flux of the two averages at t_n
+ * before the step is judged; see step.c. */
 int orc_step1d(const orc_cfg *cfg, int n, double dx, double dt,
                const double *in, double *out, const unsigned char *flags);
 int orc_step2d(const orc_cfg *cfg, int nx, int ny, double dx, double dy,

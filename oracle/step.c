@@ -174,6 +174,44 @@ static void recon_cell1d(const orc_cfg *cfg, int n, double dx, const double *st,
     }
 }
 
+/* Positivity safeguard (an addition to the paper's scheme, which has no
+ * limiter; used only when cfg->positivity is set).  A cell is troubled when
+ * its update from the face fluxes Fh (Step 5) would be non-physical.  Every
+ * face next to a troubled cell takes the first-order HLLE flux of the two
+ * cell averages at t_n instead (ghost cells by the boundary conditions;
+ * Einfeldt's wave-speed bounds, with which the first-order scheme keeps
+ * density and pressure positive), its state at x/t = 0 standing for the face
+ * value at t_{n+1} in the derivative averages.  Both cells of a face see the
+ * same flux, so the update stays conservative.  One round: a cell that is
+ * still non-physical fails the step. */
+static void first_order_faces(const orc_cfg *cfg, int n, double dx, double dt,
+                              const double *in, double *Fh, double *We)
+{
+    int m = orc_ncomp(cfg->eq, 1);
+    unsigned char *trouble = malloc((size_t)n);
+    for (int j = 0; j < n; ++j) {
+        double Wn[4];
+        for (int c = 0; c < m; ++c)
+            Wn[c] = in[c * n + j] - dt / dx * (Fh[(j + 1) * m + c] - Fh[j * m + c]);
+        trouble[j] = (unsigned char)nonphysical(cfg, 1, Wn);
+    }
+    for (int f = 0; f <= n; ++f) {
+        /* the cells on both sides; a ghost stands for the cell it copies */
+        int l = source_index(cfg->bc[0], n, f - 1);
+        int r = source_index(cfg->bc[1], n, f);
+        if (!trouble[l] && !trouble[r]) continue;
+        double WL[4], VL[4], WR[4], VR[4], Ws[4], F[4];
+        orc_cell1d(cfg, n, in, f - 1, WL, VL);
+        orc_cell1d(cfg, n, in, f, WR, VR);
+        orc_hlle(cfg->gamma, 1, WL, WR, F, Ws);
+        for (int c = 0; c < m; ++c) {
+            Fh[f * m + c] = F[c];
+            We[f * m + c] = Ws[c];
+        }
+    }
+    free(trouble);
+}
+
 int orc_step1d(const orc_cfg *cfg, int n, double dx, double dt,
                const double *in, double *out, const unsigned char *flags)
 {
@@ -212,6 +250,7 @@ int orc_step1d(const orc_cfg *cfg, int n, double dx, double dt,
         }
         for (int c = 0; c < m; ++c) Fh[f * m + c] = acc[c];
     }
+    if (cfg->positivity && cfg->eq == ORC_EULER) first_order_faces(cfg, n, dx, dt, in, Fh, We);
     /* Step 5: update of averages and derivative averages */
     int bad = 0;
     for (int j = 0; j < n; ++j) {

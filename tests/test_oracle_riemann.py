@@ -83,6 +83,61 @@ def test_hllc_state_consistency():
     np.testing.assert_allclose(O.hllc_state(G, W, W), W, rtol=1e-14)
 
 
+# ---- HLLE (the positivity safeguard's first-order flux) ----------------------
+
+def einfeldt_bounds(WL, WR, g=G):
+    """Wave-speed bounds of Einfeldt (1988): the sides' acoustic speeds and the
+    Roe-averaged ones."""
+    def prim(W):
+        rho, m, E = W
+        u = m / rho
+        return rho, u, (g - 1) * (E - 0.5 * rho * u * u)
+    (rl, ul, pl), (rr, ur, pr) = prim(WL), prim(WR)
+    hl, hr = (WL[2] + pl) / rl, (WR[2] + pr) / rr
+    a, b = np.sqrt(rl), np.sqrt(rr)
+    ut, ht = (a * ul + b * ur) / (a + b), (a * hl + b * hr) / (a + b)
+    ct = np.sqrt((g - 1) * (ht - 0.5 * ut * ut))
+    return min(ul - np.sqrt(g * pl / rl), ut - ct), max(ur + np.sqrt(g * pr / rr), ut + ct)
+
+
+@pytest.mark.parametrize("left,right", [((1.0, -2.0, 0.4), (1.0, 2.0, 0.4)),
+                                        ((1.0, -0.5, 1.0), (0.4, 1.5, 0.3)),
+                                        ((2.0, -1.5, 3.0), (0.8, 1.2, 0.7))])
+def test_hlle_state_is_the_exact_fan_average(left, right):
+    """Double rarefactions, whose exact fan runs from u_L - c_L to u_R + c_R,
+    speeds among Einfeldt's bounds: the bounds contain the fan, and the HLLE
+    state is the mean of the exact Riemann solution over it (the integral
+    form of the conservation law over [S_L t, S_R t]); its flux meets the jump
+    condition across the left bound.  (With a shock the bounds may fall inside
+    the fan, which the scheme allows: its positivity rests on the bounds
+    covering the Roe-averaged wave speeds.)"""
+    WL, WR = prim_to_cons(*left), prim_to_cons(*right)
+    assert O.exact_riemann(G, left, right, 0.0)[1] < min(left[2], right[2])   # two rarefactions
+    SL, SR = einfeldt_bounds(WL, WR)
+    assert SL < 0 < SR
+    outside = [O.exact_riemann(G, left, right, s)[0] for s in (SL - 1e-9, SR + 1e-9)]
+    np.testing.assert_allclose(outside[0], left, rtol=1e-12)
+    np.testing.assert_allclose(outside[1], right, rtol=1e-12)
+    s = SL + (np.arange(20000) + 0.5) / 20000 * (SR - SL)
+    mean = np.mean([prim_to_cons(*O.exact_riemann(G, left, right, x)[0]) for x in s], axis=0)
+    F, Ws = O.hlle(G, WL, WR)
+    np.testing.assert_allclose(Ws, mean, rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(F, flux(WL) + SL * (Ws - WL), rtol=1e-12, atol=1e-12)
+
+
+def test_hlle_consistency_and_upwinding():
+    W = prim_to_cons(0.7, -0.2, 2.0)
+    F, Ws = O.hlle(G, W, W)
+    np.testing.assert_allclose(F, flux(W), rtol=1e-14)
+    np.testing.assert_allclose(Ws, W, rtol=1e-14)
+    WL, WR = prim_to_cons(1.0, 5.0, 1.0), prim_to_cons(0.5, 4.0, 0.4)
+    F, Ws = O.hlle(G, WL, WR)
+    np.testing.assert_allclose(F, flux(WL), rtol=1e-14)
+    np.testing.assert_array_equal(Ws, WL)
+    F, Ws = O.hlle(G, prim_to_cons(1.0, 0.8, 1.0), prim_to_cons(1.0, -0.8, 1.0))
+    assert abs(F[0]) < 1e-14 and abs(Ws[1]) < 1e-14
+
+
 # Star states of the classical shock-tube tests (Toro, Riemann Solvers and
 # Numerical Methods for Fluid Dynamics, ch. 4, table of exact solutions).
 TORO = [

@@ -333,6 +333,49 @@ def test_blast_waves_conserve_at_reflective_walls():
     assert s[0, 0].min() > 0.1 and s[0, 0].max() < 7.0
 
 
+# ---- the positivity safeguard (an addition, off by default) ------------------
+
+def test_positivity_safeguard_changes_nothing_where_it_is_not_needed():
+    """Runs that never meet a non-physical update are bit for bit the same
+    with the safeguard on."""
+    for st, dx, T, bc in ((WL.density_wave_1d(40), 2.0 / 40, 0.5, O.BC_PERIODIC),
+                          (WL.lax_tube(200), 10.0 / 200, 1.3, O.BC_TRANSMISSIVE)):
+        runs = [O.advance1d(O.Config(eq=O.EULER, bc=(bc,) * 4, positivity=p), st, dx, 0.9, T)
+                for p in (False, True)]
+        assert not runs[0][3] and not runs[1][3]
+        np.testing.assert_array_equal(runs[0][0], runs[1][0])
+
+
+def test_positivity_safeguard_is_local_and_conservative():
+    """Blast waves at 200 cells (which fail without the safeguard at step 262):
+    at every step where the unguarded update would be non-physical, the guarded
+    one is physical, equals the unguarded one bit for bit in every cell with
+    no troubled cell next to it, and has the same total mass and energy (the
+    walls' fluxes of both vanish); the whole guarded run reaches T."""
+    n = 200
+    on = O.Config(eq=O.EULER, bc=(O.BC_REFLECTIVE,) * 4, positivity=True)
+    off = O.Config(eq=O.EULER, bc=(O.BC_REFLECTIVE,) * 4)
+    st, t, hits = WL.blast_waves(n), 0.0, 0
+    while t < 0.038:
+        dt = min(O.dt1d(on, st, 1.0 / n, 0.9), 0.038 - t)
+        a, bad_off = O.step1d(off, st, 1.0 / n, dt)
+        b, bad_on = O.step1d(on, st, 1.0 / n, dt)
+        assert not bad_on
+        if bad_off:
+            hits += 1
+            rho, m, E = a[0]
+            with np.errstate(all="ignore"):
+                trouble = ~((rho > 0) & (0.4 * (E - 0.5 * m * m / rho) > 0))
+            near = trouble | np.roll(trouble, 1) | np.roll(trouble, -1)
+            near[0] |= trouble[0]                      # mirror ghosts
+            near[-1] |= trouble[-1]
+            np.testing.assert_array_equal(a[:, :, ~near], b[:, :, ~near])
+            for c in (0, 2):
+                assert abs(b[0, c].sum() - st[0, c].sum()) <= 1e-13 * st[0, c].sum()
+        st, t = b, t + dt
+    assert hits > 0
+
+
 def test_transmissive_boundary_keeps_constant_state():
     cfg = O.Config(eq=O.EULER, bc=(O.BC_TRANSMISSIVE,) * 4)
     W = WL.prim_to_cons(np.full(20, 1.3), np.full(20, 0.4), np.full(20, 0.8))
