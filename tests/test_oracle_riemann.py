@@ -121,7 +121,8 @@ def test_hlle_state_is_the_exact_fan_average(left, right):
     s = SL + (np.arange(20000) + 0.5) / 20000 * (SR - SL)
     mean = np.mean([prim_to_cons(*O.exact_riemann(G, left, right, x)[0]) for x in s], axis=0)
     F, Ws = O.hlle(G, WL, WR)
-    np.testing.assert_allclose(Ws, mean, rtol=1e-6, atol=1e-9)
+    # midpoint rule over 20000 points: first order at the kinks of the fan's edges
+    np.testing.assert_allclose(Ws, mean, rtol=2e-5, atol=1e-9)
     np.testing.assert_allclose(F, flux(WL) + SL * (Ws - WL), rtol=1e-12, atol=1e-12)
 
 
