@@ -119,6 +119,35 @@ def exact_density(d, t, sub=16):
     return out.mean(axis=1)
 
 
+def positivity_leg(S, insts, meshes, init, args, plain_value):
+    """The same job with the positivity safeguard on (not in the paper; the
+    headline value is the paper's scheme without it): throughput and the
+    instances that still stop on a non-physical state."""
+    import torch
+    log("positivity safeguard ...")
+    s = S.Solver(meshes, S.Params.make(eq=S.EULER, cfl=0.9, positivity=True), device="cuda:0")
+    zeros = np.zeros(COUNT)
+    T = np.full(COUNT, T_END)
+    ncell = np.array([d.n for d in insts], dtype=np.int64)
+    for _ in range(args.warmup):
+        s.state.copy_(init)
+        s.set_times(zeros)
+        s.advance_to(T, raise_nonphysical=False)
+    torch.cuda.synchronize()
+    cus = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.state.copy_(init)
+        s.set_times(zeros)
+        cus.append(int((ncell * s.advance_to(T, raise_nonphysical=False)).sum()))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    value = float(np.mean(cus)) * args.steps / wall
+    return {"value": value, "unit": "cell-updates/s", "vs_plain": value / plain_value,
+            "ms_per_step": wall / args.steps * 1e3, "cell_updates_per_step": float(np.mean(cus)),
+            "nonphysical_instances": int((s.instance_status() != 0).sum())}
+
+
 def gated_leg(S, insts, states, meshes, init, args, plain_value, plain):
     """The same job with the learned gate: network trained on the GPU from
     plain runs of separate seeded problems (untimed), then K timed steps; L1
@@ -377,6 +406,7 @@ def main():
         del src, dst
     if not args.no_gate:
         out["gated"] = gated_leg(S, insts, states, meshes, init, args, value, solver)
+        out["positivity"] = positivity_leg(S, insts, meshes, init, args, value)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(insts, states)

@@ -52,14 +52,16 @@ class Params(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("adv_a", ctypes.c_double),
                 ("adv_b", ctypes.c_double), ("cfl", ctypes.c_double), ("eps", ctypes.c_double),
                 ("lin_w", ctypes.c_double * 3), ("gate_threshold", ctypes.c_double),
-                ("gate_every", ctypes.c_int)]
+                ("gate_every", ctypes.c_int), ("positivity", ctypes.c_int)]
 
     @classmethod
     def make(cls, eq=EULER, charwise=True, weights=W_NONLINEAR, gamma=1.4, adv_a=1.0,
              adv_b=0.0, cfl=0.9, eps=1e-6, lin_w=(0.994, 0.003, 0.003), gate_threshold=0.5,
-             gate_every=1):
+             gate_every=1, positivity=False):
+        """positivity: the 1D Euler safeguard (not in the paper; off = the
+        paper's scheme)."""
         return cls(eq, int(charwise), weights, gamma, adv_a, adv_b, cfl, eps,
-                   (ctypes.c_double * 3)(*lin_w), gate_threshold, gate_every)
+                   (ctypes.c_double * 3)(*lin_w), gate_threshold, gate_every, int(positivity))
 
 
 _lib = None

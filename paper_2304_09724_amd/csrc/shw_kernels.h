@@ -56,6 +56,10 @@ struct Loop1D {
     int gate_every;            // LEARNED: evaluate the network every this many steps
     double share;              // cell-updates per workgroup if the launch's estimated work
                                // were spread evenly; > 0 turns on work-based wave priority
+    double *faces;             // positivity safeguard (NULL: off): per instance, planes
+                               // [2M][n+1] of each face's flux and value at t_{n+1},
+                               // instance i at 2M (cell_off + i)
+    uint8_t *trouble;          // safeguard: one byte per cell
 };
 
 // Launch parameters of one 2D step over a batch (all pointers device-side).
@@ -100,7 +104,7 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, int t, floa
 
 hipError_t launch_loop1d(int eq, const Loop1D &L, const DevParams &P, int grid, int variant,
                          hipStream_t stream);
-int loop1d_max_blocks(int eq, int variant, bool learned);
+int loop1d_max_blocks(int eq, int variant, bool learned, bool guard);
 hipError_t launch_dt1d(int eq, const Inst1D *inst, int n_inst, const double *state,
                        const DevParams &P, double *dt_out, hipStream_t stream);
 

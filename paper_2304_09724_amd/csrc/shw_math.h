@@ -248,6 +248,48 @@ SHW_HD void hllc_state(const R *WL, const R *WR, double gamma, R *Ws)
     Ws[M - 1] = f * (WK[M - 1] * irk + (Ss - uk) * (Ss + pk / mk));
 }
 
+// First-order HLLE flux F and state Ws at x/t = 0 in the normal direction x
+// (the positivity safeguard's face, not part of the paper's scheme): a single
+// intermediate state between wave-speed bounds after Einfeldt (1988), the
+// smaller and larger of the sides' acoustic speeds and of the speeds of the
+// Roe average (sqrt(rho) weights on u, v and the enthalpy).  With these bounds
+// the first-order scheme keeps density and pressure positive.
+template <int DIM, class R>
+SHW_HD void hlle_face(const R *WL, const R *WR, const DevParams &P, R *F, R *Ws)
+{
+    constexpr int M = NComp<EULER, DIM>::M;
+    const double g = P.gamma;
+    const R irl = 1.0 / WL[0], irr = 1.0 / WR[0];
+    const R ul = WL[1] * irl, ur = WR[1] * irr;
+    R vl = 0.0, vr = 0.0;
+    if constexpr (DIM == 2) { vl = WL[2] * irl; vr = WR[2] * irr; }
+    const R pl = pressure<DIM>(WL, g), pr = pressure<DIM>(WR, g);
+    const R sl = sqrt(WL[0]), sr = sqrt(WR[0]), iw = 1.0 / (sl + sr);
+    const R ut = (sl * ul + sr * ur) * iw, vt = (sl * vl + sr * vr) * iw;
+    const R ht = (sl * ((WL[M - 1] + pl) * irl) + sr * ((WR[M - 1] + pr) * irr)) * iw;
+    const R ct = sqrt((g - 1.0) * (ht - 0.5 * (ut * ut + vt * vt)));
+    const R SL = fmin(ul - sqrt(g * pl * irl), ut - ct);
+    const R SR = fmax(ur + sqrt(g * pr * irr), ut + ct);
+    R FL[M], FR[M];
+    phys_flux_x<EULER, DIM>(WL, P, FL);
+    phys_flux_x<EULER, DIM>(WR, P, FR);
+    if (0.0 <= SL || SR <= 0.0) {
+        const bool left = 0.0 <= SL;
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            F[c] = left ? FL[c] : FR[c];
+            Ws[c] = left ? WL[c] : WR[c];
+        }
+        return;
+    }
+    const R id = 1.0 / (SR - SL);
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        F[c] = (SR * FL[c] - SL * FR[c] + SL * SR * (WR[c] - WL[c])) * id;
+        Ws[c] = (SR * WR[c] - SL * WL[c] - (FR[c] - FL[c])) * id;
+    }
+}
+
 // Upwind solution at x/t = 0 of a linear Riemann problem with speed lam; a
 // speed below 1e-10 of the system's fastest speed counts as zero and takes
 // the mean (a rounding-level speed must not pick a side).

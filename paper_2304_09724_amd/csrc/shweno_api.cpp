@@ -37,6 +37,7 @@ bool valid_params(const shw_params *p)
     for (int k = 0; k < 3; ++k)
         if (!(p->lin_w[k] > 0.0)) return false;
     if (std::fabs(p->lin_w[0] + p->lin_w[1] + p->lin_w[2] - 1.0) > 1e-12) return false;
+    if (p->positivity != 0 && p->positivity != 1) return false;
     return true;
 }
 
@@ -69,7 +70,8 @@ constexpr int lines2d(int v) { return 1 << v; }
 struct Layout {
     size_t alt = 0, inst = 0, order = 0, queue = 0, ist = 0, t_end = 0, dt = 0,
            flags = 0, tiles0 = 0, tiles1 = 0, parity = 0, last = 0, dt_fixed = 0,
-           steps_left = 0, smax = 0, bad = 0, active = 0, gate = 0, total = 0;
+           steps_left = 0, smax = 0, bad = 0, active = 0, gate = 0, faces = 0, trouble = 0,
+           total = 0;
 };
 
 Layout make_layout(const shw_mesh *meshes, int n_inst, const shw_params *p)
@@ -100,6 +102,10 @@ Layout make_layout(const shw_mesh *meshes, int n_inst, const shw_params *p)
     L.bad = take((size_t)n_inst * sizeof(int));
     L.active = take(256);
     L.gate = take(64 * sizeof(GateLane));
+    // positivity safeguard (1D Euler): each face's flux and value at t_{n+1},
+    // planes [6][n+1] per instance, and a byte per cell
+    L.faces = take(p->positivity ? (cells + (size_t)n_inst) * 6 * sizeof(double) : 0);
+    L.trouble = take(p->positivity ? cells : 0);
     L.total = off;
     return L;
 }
@@ -167,6 +173,7 @@ static bool valid_batch(const shw_mesh *meshes, int n_inst, const shw_params *pa
         if (!valid_mesh(&meshes[i]) || meshes[i].dim != meshes[0].dim) return false;
     if (params->eq == SHW_BURGERS && meshes[0].dim != 1) return false;
     if (params->weights == SHW_W_LEARNED && params->eq != SHW_EULER) return false;
+    if (params->positivity && (params->eq != SHW_EULER || meshes[0].dim != 1)) return false;
     return true;
 }
 
@@ -254,7 +261,8 @@ shw_status shw_create(const shw_mesh *meshes, int n_inst, const shw_params *para
         s = c->hip(hipMemcpyAsync(c->ws + c->lay.inst, i1.data(), i1.size() * sizeof(Inst1D),
                                   hipMemcpyHostToDevice, c->stream), "copy instances");
         c->variant = 1;
-        c->grid1d = loop1d_max_blocks(params->eq, c->variant, params->weights == SHW_W_LEARNED);
+        c->grid1d = loop1d_max_blocks(params->eq, c->variant, params->weights == SHW_W_LEARNED,
+                                      params->positivity != 0);
     } else {
         s = c->hip(hipMemcpyAsync(c->ws + c->lay.inst, i2.data(), i2.size() * sizeof(Inst2D),
                                   hipMemcpyHostToDevice, c->stream), "copy instances");
@@ -455,6 +463,10 @@ static Loop1D loop_args(shw_ctx *c)
     const double th = c->params.gate_threshold;
     L.gate_logit_min = (th > 0.0 && th < 1.0) ? (float)std::log(th / (1.0 - th)) : 0.0f;
     L.gate_every = c->params.gate_every > 0 ? c->params.gate_every : 1;
+    if (c->params.positivity) {
+        L.faces = c->at<double>(c->lay.faces);
+        L.trouble = c->at<uint8_t>(c->lay.trouble);
+    }
     return L;
 }
 
@@ -566,7 +578,8 @@ shw_status shw_set_tile(shw_ctx *c, int variant)
     }
     c->variant = variant;
     if (c->dim == 1)
-        c->grid1d = loop1d_max_blocks(c->params.eq, variant, c->params.weights == SHW_W_LEARNED);
+        c->grid1d = loop1d_max_blocks(c->params.eq, variant, c->params.weights == SHW_W_LEARNED,
+                                          c->params.positivity != 0);
     return SHW_OK;
 }
 

@@ -60,13 +60,13 @@ __device__ __forceinline__ int flag_cell(int q, int n, int bc_lo, int bc_hi)
     return q;
 }
 
-template <int EQ, int NB, bool LRN>
+template <int EQ, int NB, bool LRN, bool GUARD>
 __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__restrict__ src,
                                                double *__restrict__ dst, double dt,
                                                const DevParams &P,
                                                uint8_t *__restrict__ flags, const u32x4 *gate,
                                                float gate_logit_min, int gate_since,
-                                               double *spd_out)
+                                               double *spd_out, double *__restrict__ faces)
 {
     constexpr int M = NComp<EQ, 1>::M;
     const int lane = threadIdx.x % WAVE;
@@ -128,6 +128,16 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
 #pragma unroll
             for (int c = 0; c < M; ++c) { Fh[c] = 0.0; We[c] = 0.0; }
         }
+        if constexpr (GUARD) {
+            if (lane >= 1 && lane <= CHUNK && j >= 0 && j <= n) {
+                // the safeguard's record of face j - 1/2 (each face once)
+#pragma unroll
+                for (int c = 0; c < M; ++c) {
+                    faces[c * (n + 1) + j] = Fh[c];
+                    faces[(M + c) * (n + 1) + j] = We[c];
+                }
+            }
+        }
         double Fn[M], Wn[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) {
@@ -149,6 +159,86 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
     // the next step's CFL speed, one value per wave (a0.. of spd_out)
     spd = wave_max(spd);
     if (lane == 0) spd_out[wave] = spd;
+    return bad;
+}
+
+// Positivity safeguard (an addition to the paper's scheme, which has no
+// limiter; on when the launch carries face records).  After a sweep that left
+// a non-physical average, a cell is troubled when its new average is
+// non-physical (the test written as p = (g-1)(E - m^2/(2 rho)) > 0, so the
+// decision rounds as a plain evaluation of that formula does).  Every face
+// next to a troubled cell takes the first-order HLLE flux of the two averages
+// at t_n instead, its state at x/t = 0 standing for the face value at t_{n+1};
+// the cells on both sides of such a face are updated again from the sweep's
+// records of their other face, so the step stays conservative.  One round:
+// a cell still non-physical fails the instance as before.  The wave speeds of
+// all new averages are reduced again for the next step.  Returns true if a
+// cell of this thread is still non-physical.
+__device__ __forceinline__ bool troubled(const double W[3], const DevParams &P)
+{
+    if (!isfinite(W[0]) || !isfinite(W[1]) || !isfinite(W[2]) || !(W[0] > 0.0)) return true;
+    const double ke = 0.5 * W[1] * W[1] / W[0];
+    return !((P.gamma - 1.0) * (W[2] - ke) > 0.0);
+}
+
+template <int NB>
+__device__ bool guard_instance(const Inst1D &d, const double *__restrict__ src,
+                               double *__restrict__ dst, double dt, const DevParams &P,
+                               const double *__restrict__ faces, uint8_t *__restrict__ trouble,
+                               double *spd_out)
+{
+    constexpr int M = 3;
+    const int n = d.n, nf = n + 1;
+    for (int j = threadIdx.x; j < n; j += NB) {
+        const double W[M] = {dst[j], dst[n + j], dst[2 * n + j]};
+        trouble[j] = (uint8_t)troubled(W, P);
+    }
+    __syncthreads();
+    const double idx = 1.0 / d.dx, dt_dx = dt * idx;
+    bool bad = false;
+    double spd = 0.0;
+    for (int j = threadIdx.x; j < n; j += NB) {
+        // the neighbours' indices; a ghost stands for the cell it copies
+        const int jl = j > 0 ? j - 1 : (d.bc_lo == BC_PERIODIC ? n - 1 : 0);
+        const int jr = j < n - 1 ? j + 1 : (d.bc_hi == BC_PERIODIC ? 0 : n - 1);
+        const bool tj = trouble[j] != 0;
+        const bool fl = tj || trouble[jl] != 0, fr = tj || trouble[jr] != 0;
+        double W[M];
+        if (fl || fr) {
+            double W0[M], V0[M], Wx[M], Vx[M], FL[M], EL[M], FR[M], ER[M], Vn[M];
+            load_cell<EULER, M>(src, n, j, d.bc_lo, d.bc_hi, W0, V0);
+            if (fl) {
+                load_cell<EULER, M>(src, n, j - 1, d.bc_lo, d.bc_hi, Wx, Vx);
+                hlle_face<1>(Wx, W0, P, FL, EL);
+            } else {
+#pragma unroll
+                for (int c = 0; c < M; ++c) { FL[c] = faces[c * nf + j]; EL[c] = faces[(M + c) * nf + j]; }
+            }
+            if (fr) {
+                load_cell<EULER, M>(src, n, j + 1, d.bc_lo, d.bc_hi, Wx, Vx);
+                hlle_face<1>(W0, Wx, P, FR, ER);
+            } else {
+#pragma unroll
+                for (int c = 0; c < M; ++c) {
+                    FR[c] = faces[c * nf + j + 1];
+                    ER[c] = faces[(M + c) * nf + j + 1];
+                }
+            }
+            update1d<M>(W0, FL, FR, EL, ER, dt_dx, idx, W, Vn);
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                dst[c * n + j] = W[c];
+                dst[(M + c) * n + j] = Vn[c];
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < M; ++c) W[c] = dst[c * n + j];
+        }
+        bad |= bad_state<EULER>(W, P);
+        spd = fmax(spd, wave_speed<EULER>(W, P));
+    }
+    spd = wave_max(spd);
+    if (threadIdx.x % WAVE == 0) spd_out[threadIdx.x / WAVE] = spd;
     return bad;
 }
 
@@ -174,7 +264,7 @@ __device__ inline void work_priority(double work, double share)
 
 // Two waves per SIMD (at most 256 registers a lane) is the occupancy the
 // kernel is written for: one wave alone cannot hide its FP64 latencies.
-template <int EQ, int NB, bool LRN>
+template <int EQ, int NB, bool LRN, bool GUARD>
 __global__ void __launch_bounds__(NB) __attribute__((amdgpu_waves_per_eu(2)))
 loop1d_kernel(Loop1D Lp, DevParams P)
 {
@@ -246,13 +336,22 @@ loop1d_kernel(Loop1D Lp, DevParams P)
             // steps of the instance; steps are separated by block barriers, so
             // the decisions one wave stores are seen by the other waves
             gate_since = (k == 0 || (st.steps + k) % Lp.gate_every == 0) ? 0 : gate_since + 1;
-            const bool bad = sweep_instance<EQ, NB, LRN>(d, A, B, dt, P, Lp.flags, s_gate,
-                                                         Lp.gate_logit_min, gate_since,
-                                                         s_spd[buf ^ 1]);
+            double *faces = GUARD ? Lp.faces + 2LL * M * (d.cell_off + i) : nullptr;
+            const bool bad = sweep_instance<EQ, NB, LRN, GUARD>(d, A, B, dt, P, Lp.flags, s_gate,
+                                                                Lp.gate_logit_min, gate_since,
+                                                                s_spd[buf ^ 1], faces);
             // a full barrier (with workgroup fences) orders the speeds in LDS and
             // the gate's stored decisions for the next step
             __syncthreads();
-            const int any_bad = __syncthreads_or(bad);
+            int any_bad = __syncthreads_or(bad);
+            if constexpr (GUARD) {
+                if (any_bad) {
+                    const bool still = guard_instance<NB>(d, A, B, dt, P, faces,
+                                                          Lp.trouble + d.cell_off, s_spd[buf ^ 1]);
+                    __syncthreads();
+                    any_bad = __syncthreads_or(still);
+                }
+            }
             buf ^= 1;
             double *tmp = A; A = B; B = tmp;
             ++k;
@@ -307,30 +406,27 @@ __global__ void zero_int_kernel(int *p) { *p = 0; }
 // workgroup size of tile variant v: 2, 4 or 8 waves per instance
 static int loop1d_threads(int v) { return v == 0 ? 128 : v == 2 ? 512 : 256; }
 
+// The kernel instance for an equation and mode: the learned gate (Euler) and
+// the positivity safeguard (Euler) are instances of their own, so the
+// paper's scheme runs with neither one's code in its register budget.
 template <int NB>
-static void launch_loop1d_nb(int eq, const Loop1D &L, const DevParams &P, int grid,
-                             hipStream_t stream)
+static const void *loop1d_fn(int eq, bool learned, bool guard)
 {
-    if (eq == EULER && P.weights == W_LEARNED) loop1d_kernel<EULER, NB, true><<<grid, NB, 0, stream>>>(L, P);
-    else if (eq == EULER) loop1d_kernel<EULER, NB, false><<<grid, NB, 0, stream>>>(L, P);
-    else if (eq == BURG) loop1d_kernel<BURG, NB, false><<<grid, NB, 0, stream>>>(L, P);
-    else loop1d_kernel<ADV, NB, false><<<grid, NB, 0, stream>>>(L, P);
+    if (eq == EULER) {
+        if (learned)
+            return guard ? (const void *)loop1d_kernel<EULER, NB, true, true>
+                         : (const void *)loop1d_kernel<EULER, NB, true, false>;
+        return guard ? (const void *)loop1d_kernel<EULER, NB, false, true>
+                     : (const void *)loop1d_kernel<EULER, NB, false, false>;
+    }
+    if (eq == BURG) return (const void *)loop1d_kernel<BURG, NB, false, false>;
+    return (const void *)loop1d_kernel<ADV, NB, false, false>;
 }
 
-template <int NB>
-static int loop1d_per_cu(int eq, bool learned)
+static const void *loop1d_fn(int eq, bool learned, bool guard, int nb)
 {
-    int per_cu = 0;
-    hipError_t e;
-    if (eq == EULER && learned)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop1d_kernel<EULER, NB, true>, NB, 0);
-    else if (eq == EULER)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop1d_kernel<EULER, NB, false>, NB, 0);
-    else if (eq == BURG)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop1d_kernel<BURG, NB, false>, NB, 0);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, loop1d_kernel<ADV, NB, false>, NB, 0);
-    return (e != hipSuccess || per_cu < 1) ? 1 : per_cu;
+    return nb == 128 ? loop1d_fn<128>(eq, learned, guard)
+           : nb == 512 ? loop1d_fn<512>(eq, learned, guard) : loop1d_fn<256>(eq, learned, guard);
 }
 
 hipError_t launch_loop1d(int eq, const Loop1D &L, const DevParams &P, int grid, int variant,
@@ -338,17 +434,21 @@ hipError_t launch_loop1d(int eq, const Loop1D &L, const DevParams &P, int grid, 
 {
     zero_int_kernel<<<1, 1, 0, stream>>>(L.queue);
     const int nb = loop1d_threads(variant);
-    if (nb == 128) launch_loop1d_nb<128>(eq, L, P, grid, stream);
-    else if (nb == 512) launch_loop1d_nb<512>(eq, L, P, grid, stream);
-    else launch_loop1d_nb<256>(eq, L, P, grid, stream);
-    return hipGetLastError();
+    const bool guard = eq == EULER && L.faces != nullptr;
+    Loop1D l = L;
+    DevParams p = P;
+    void *args[] = {&l, &p};
+    return hipLaunchKernel(loop1d_fn(eq, P.weights == W_LEARNED, guard, nb), dim3(grid), dim3(nb),
+                           args, 0, stream);
 }
 
-int loop1d_max_blocks(int eq, int variant, bool learned)
+int loop1d_max_blocks(int eq, int variant, bool learned, bool guard)
 {
     const int nb = loop1d_threads(variant);
-    const int per_cu = nb == 128 ? loop1d_per_cu<128>(eq, learned)
-                       : nb == 512 ? loop1d_per_cu<512>(eq, learned) : loop1d_per_cu<256>(eq, learned);
+    int per_cu = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, loop1d_fn(eq, learned, guard && eq == EULER, nb), nb, 0);
+    if (e != hipSuccess || per_cu < 1) per_cu = 1;
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);

@@ -76,6 +76,18 @@ def test_learned_gate_is_euler_only():
         assert workspace(mesh, p) == 0
 
 
+def test_positivity_safeguard_is_1d_euler_only():
+    rect = S.Mesh.rect(16, 16, 0.0, 1.0, 0.0, 1.0)
+    on = S.Params.make(eq=S.EULER, positivity=True)
+    off = S.Params.make(eq=S.EULER)
+    assert workspace(line(), on) > workspace(line(), off) > 0
+    assert workspace(rect, on) == 0
+    assert workspace(line(), S.Params.make(eq=S.BURGERS, positivity=True)) == 0
+    bad = S.Params.make(eq=S.EULER)
+    bad.positivity = 2
+    assert state_doubles(line(), bad) == 0
+
+
 def test_burgers_is_1d_only():
     rect = S.Mesh.rect(16, 16, 0.0, 1.0, 0.0, 1.0)
     assert workspace(line(), S.Params.make(eq=S.BURGERS)) > 0

@@ -147,6 +147,72 @@ def test_blast_waves_full_runs():
     assert rel_err(s.get_state(1), res[1][0]) < TOL
 
 
+def test_positivity_safeguard_blast_waves():
+    """The blast waves with the safeguard on (not in the paper): all three
+    meshes reach T = 0.038, each whole run against the oracle's with the same
+    safeguard (at 200 and 800 cells the unguarded scheme fails)."""
+    ns = [200, 400, 800]
+    s = S.Solver([S.Mesh.line(n, 0.0, 1.0, S.BC_REFLECTIVE) for n in ns],
+                 S.Params.make(eq=S.EULER, positivity=True))
+    for i, n in enumerate(ns):
+        s.set_state(i, WL.blast_waves(n))
+    steps = s.advance_to(np.full(len(ns), 0.038))
+    cfg = O.Config(eq=O.EULER, bc=(O.BC_REFLECTIVE,) * 4, positivity=True)
+    with cf.ThreadPoolExecutor(3) as ex:
+        res = list(ex.map(lambda n: O.advance1d(cfg, WL.blast_waves(n), 1.0 / n, 0.9, 0.038), ns))
+    for i, (o, t, osteps, bad) in enumerate(res):
+        assert not bad and steps[i] == osteps, (ns[i], steps[i], osteps)
+        assert rel_err(s.get_state(i), o) < TOL, ns[i]
+
+
+def test_positivity_safeguard_leaves_other_runs_unchanged():
+    """A ragged Riemann batch that never needs the safeguard: bit for bit the
+    same states with it on and off."""
+    insts = WL.riemann_batch_1d(count=12, seed=7, nmin=20, nmax=300)
+    meshes = [S.Mesh.line(d.n, d.x0, d.x1, S.BC_TRANSMISSIVE) for d in insts]
+    runs = []
+    for pos in (False, True):
+        s = S.Solver(meshes, S.Params.make(eq=S.EULER, positivity=pos))
+        for i, d in enumerate(insts):
+            s.set_state(i, d.state())
+        s.advance_to(0.14)
+        runs.append([s.get_state(i) for i in range(len(insts))])
+    for a, b in zip(*runs):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_positivity_safeguard_on_the_batch_failures():
+    """The instances of the 4096-problem batch that meet a non-physical state
+    under the paper's scheme, run again with the safeguard: all complete,
+    and on a sample of six the status, the step count and the state agree
+    with the oracle's run with the same safeguard."""
+    insts = WL.riemann_batch_1d(count=4096, T=0.14)
+    meshes = [S.Mesh.line(d.n, d.x0, d.x1, S.BC_TRANSMISSIVE) for d in insts]
+    s = S.Solver(meshes, S.Params.make(eq=S.EULER))
+    for i, d in enumerate(insts):
+        s.set_state(i, d.state())
+    s.advance_to(np.full(len(insts), 0.14), raise_nonphysical=False)
+    failed = np.nonzero(s.instance_status() != 0)[0]
+    assert len(failed) > 50
+    sub = [insts[i] for i in failed]
+    g = S.Solver([meshes[i] for i in failed], S.Params.make(eq=S.EULER, positivity=True))
+    for k, d in enumerate(sub):
+        g.set_state(k, d.state())
+    steps = g.advance_to(np.full(len(sub), 0.14), raise_nonphysical=False)
+    codes = g.instance_status()
+    print(f"{len(failed)} failures without the safeguard, {int((codes != 0).sum())} with it")
+    assert (codes != 0).sum() == 0
+    cfg = O.Config(eq=O.EULER, bc=(O.BC_TRANSMISSIVE,) * 4, positivity=True)
+    rng = np.random.default_rng(11)
+    pick = sorted(rng.choice(len(sub), 6, replace=False))
+    with cf.ThreadPoolExecutor(6) as ex:
+        res = list(ex.map(lambda k: O.advance1d(cfg, sub[k].state(), sub[k].dx, 0.9, 0.14), pick))
+    for k, (o, t, osteps, bad) in zip(pick, res):
+        assert (codes[k] != 0) == bool(bad) and steps[k] == osteps, (k, steps[k], osteps)
+        if not bad:
+            assert rel_err(g.get_state(k), o) < TOL, k
+
+
 def test_compute_dt_matches_oracle():
     insts = WL.riemann_batch_1d(count=6, nmin=40, nmax=200)
     s = S.Solver([S.Mesh.line(d.n, d.x0, d.x1, S.BC_TRANSMISSIVE) for d in insts], gparams(S.EULER))
