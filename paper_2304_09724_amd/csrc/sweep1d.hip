@@ -41,6 +41,26 @@ __device__ __forceinline__ bool bad_state(const double *W, const DevParams &P)
     return bad;
 }
 
+// Neighbour exchange inside a wave without the LDS path: the DPP wavefront
+// shifts of the GFX9 family move a 32-bit value one lane up ("wave_shr:1",
+// lane l receives lane l - 1) or down ("wave_shl:1", lane l receives lane
+// l + 1) inside the register file.  The lane left without a neighbour keeps
+// 0; the sweep never reads it (lane 0 solves no face, lane 63 updates no
+// cell).
+constexpr int DPP_WAVE_SHL1 = 0x130;
+constexpr int DPP_WAVE_SHR1 = 0x138;
+
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double from_lane_below(double x) { return lane_shift<DPP_WAVE_SHR1>(x); }
+__device__ __forceinline__ double from_lane_above(double x) { return lane_shift<DPP_WAVE_SHL1>(x); }
+
 __device__ __forceinline__ double wave_max(double v)
 {
 #pragma unroll
@@ -120,7 +140,7 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
 #pragma unroll
         for (int a = 0; a < 5; ++a)
 #pragma unroll
-            for (int c = 0; c < M; ++c) prev[a][c] = __shfl_up(hi[a][c], 1, WAVE);
+            for (int c = 0; c < M; ++c) prev[a][c] = from_lane_below(hi[a][c]);
         double Fh[M], We[M];
         if (lane >= 1 && j >= 0 && live) {
             face1d<EQ, M>(prev, lo, dt, P, Fh, We);
@@ -141,8 +161,8 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
         double Fn[M], Wn[M];
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-            Fn[c] = __shfl_down(Fh[c], 1, WAVE);
-            Wn[c] = __shfl_down(We[c], 1, WAVE);
+            Fn[c] = from_lane_above(Fh[c]);
+            Wn[c] = from_lane_above(We[c]);
         }
         if (lane >= 1 && lane <= CHUNK && j >= 0 && j < n) {
             double Wnew[M], Vnew[M];
