@@ -44,7 +44,8 @@ def log(msg):
 # two counter runs summarised in profiles/ (FETCH_SIZE and WRITE_SIZE scaled by
 # a 1 GiB copy); valid only for the kernel sources those runs measured.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "loop1d_euler_riemann4096_hbm_counters.md")
-KERNEL_SOURCES = ["sweep1d.hip", "shw_kernels.h", "sweep1d_math.h", "shw_math.h", "gate_math.h"]
+KERNEL_SOURCES = ["sweep1d.hip", "shw_kernels.h", "sweep1d_math.h", "shw_math.h", "gate_math.h",
+                  "lanes.h"]
 
 
 def kernel_fingerprint():

@@ -16,6 +16,7 @@
 // eq. (flux), Remark 2).  The face results move one lane down and lanes 1..62
 // update their cells (Step 5, eq. (cons) and eqs. (derave), (tay1d)).  A
 // chunk advances 62 cells; lanes 0 and 63 only feed their neighbours.
+#include "lanes.h"
 #include "shw_kernels.h"
 #include "sweep1d_math.h"
 
@@ -40,26 +41,6 @@ __device__ __forceinline__ bool bad_state(const double *W, const DevParams &P)
     }
     return bad;
 }
-
-// Neighbour exchange inside a wave without the LDS path: the DPP wavefront
-// shifts of the GFX9 family move a 32-bit value one lane up ("wave_shr:1",
-// lane l receives lane l - 1) or down ("wave_shl:1", lane l receives lane
-// l + 1) inside the register file.  The lane left without a neighbour keeps
-// 0; the sweep never reads it (lane 0 solves no face, lane 63 updates no
-// cell).
-constexpr int DPP_WAVE_SHL1 = 0x130;
-constexpr int DPP_WAVE_SHR1 = 0x138;
-
-template <int CTRL>
-__device__ __forceinline__ double lane_shift(double x)
-{
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-__device__ __forceinline__ double from_lane_below(double x) { return lane_shift<DPP_WAVE_SHR1>(x); }
-__device__ __forceinline__ double from_lane_above(double x) { return lane_shift<DPP_WAVE_SHL1>(x); }
 
 __device__ __forceinline__ double wave_max(double v)
 {

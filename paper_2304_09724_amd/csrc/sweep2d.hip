@@ -14,6 +14,7 @@
 // node by node (sec. 3.1) and accumulate the flux of eq. (fx2d); lanes 2..61
 // update their cell (sec. 3, the 2D form of eq. (cons), eqs. (derave2d)).
 // The y-sweep runs the same code on the state seen with x and y exchanged.
+#include "lanes.h"
 #include "shw_kernels.h"
 #include "sweep2d_math.h"
 
@@ -211,10 +212,10 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
                 const double A = deriv_at(pw, node[g], n, sct[n]);
                 const double B = deriv_at(pv, node[g], n, sct[n]);
                 a0[c] = A;
-                am[c] = __shfl_up(A, 1, WAVE);
-                ap[c] = __shfl_down(A, 1, WAVE);
-                bm[c] = __shfl_up(B, 1, WAVE);
-                bp[c] = __shfl_down(B, 1, WAVE);
+                am[c] = from_lane_below(A);
+                ap[c] = from_lane_above(A);
+                bm[c] = from_lane_below(B);
+                bp[c] = from_lane_above(B);
             }
             double lo[5][M], hi[5][M];
             if (lane >= 1 && lane <= 62 && live) {
@@ -230,7 +231,7 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
             for (int a = 0; a + n <= 4; ++a) {
                 double JL[M];
 #pragma unroll
-                for (int c = 0; c < M; ++c) JL[c] = __shfl_up(hi[a][c], 1, WAVE);
+                for (int c = 0; c < M; ++c) JL[c] = from_lane_below(hi[a][c]);
                 if (face) {
                     if (a + n == 0) {
                         grp2d_leading<M, EQ>(JL, lo[0], P, as, G);
@@ -264,9 +265,9 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
     double Fu[M], Wu[4][M];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-        Fu[c] = __shfl_down(Fh[c], 1, WAVE);
+        Fu[c] = from_lane_above(Fh[c]);
 #pragma unroll
-        for (int g = 0; g < 4; ++g) Wu[g][c] = __shfl_down(We[g][c], 1, WAVE);
+        for (int g = 0; g < 4; ++g) Wu[g][c] = from_lane_above(We[g][c]);
     }
     if (!(lane >= 2 && lane <= 61 && s >= 0 && s < ns)) return;
     const int i = DIR == 0 ? s : t, j = DIR == 0 ? t : s;
