@@ -159,6 +159,13 @@ shw_status shw_compute_dt(shw_ctx *ctx, double *dt);
  * n_inst; entries <= 0 leave that instance alone).  Asynchronous. */
 shw_status shw_step(shw_ctx *ctx, const double *dt);
 
+/* One time step of every instance (sec. 4, Steps 1-5) with the step size its
+ * own averages give under the CFL condition, computed on the device (the
+ * shw_compute_dt value, with no end time to clamp to): the same state as
+ * shw_compute_dt followed by shw_step.  Instances stopped on a non-physical
+ * state stay stopped.  Synchronising; SHW_ENONPHYS as shw_advance_to. */
+shw_status shw_step_cfl(shw_ctx *ctx);
+
 /* Advance every instance i to time T[i] (host array) with device-computed CFL
  * steps, the last step of each instance clamped to end exactly at T[i];
  * at most max_steps steps per instance in this call.  Writes the number of

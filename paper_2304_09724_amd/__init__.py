@@ -92,6 +92,7 @@ def lib():
         L.shw_set_time.argtypes = [vp, _D]
         L.shw_compute_dt.argtypes = [vp, _D]
         L.shw_step.argtypes = [vp, _D]
+        L.shw_step_cfl.argtypes = [vp]
         L.shw_advance_to.argtypes = [vp, _D, ctypes.c_longlong, _LL]
         L.shw_instance_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int)]
         FP = ctypes.POINTER(ctypes.c_float)
@@ -261,6 +262,13 @@ class Solver:
     def step(self, dt):
         dt = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, float), (self.n,)))
         self._check(lib().shw_step(self.ctx, _dptr(dt)))
+
+    def step_cfl(self, raise_nonphysical=True):
+        """One step of every instance with the CFL step size of its own
+        averages, computed on the device."""
+        code = lib().shw_step_cfl(self.ctx)
+        if not (code == -4 and not raise_nonphysical):
+            self._check(code)
 
     def advance_to(self, T, max_steps=1_000_000, raise_nonphysical=True):
         """Advance instance i to T[i]; returns the steps taken per instance.

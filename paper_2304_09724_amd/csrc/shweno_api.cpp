@@ -736,6 +736,14 @@ shw_status shw_advance_to(shw_ctx *c, const double *T, long long max_steps, long
     return r;
 }
 
+shw_status shw_step_cfl(shw_ctx *c)
+{
+    if (!c) return SHW_EINVAL;
+    // an end time no instance reaches in one step
+    const std::vector<double> far(c->n_inst, 1e300);
+    return shw_advance_to(c, far.data(), 1, nullptr);
+}
+
 shw_status shw_set_flags(shw_ctx *c, int inst, const uint8_t *flags)
 {
     if (!c || !flags || inst < 0 || inst >= c->n_inst) return SHW_EINVAL;

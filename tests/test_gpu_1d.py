@@ -224,6 +224,25 @@ def test_compute_dt_matches_oracle():
         assert dt[i] == pytest.approx(want, rel=1e-14)
 
 
+def test_step_cfl_is_compute_dt_then_step():
+    """One device-sized CFL step equals shw_compute_dt followed by shw_step,
+    bit for bit, and advances each instance's time by its step size."""
+    insts = WL.riemann_batch_1d(count=6, nmin=40, nmax=200)
+    meshes = [S.Mesh.line(d.n, d.x0, d.x1, S.BC_TRANSMISSIVE) for d in insts]
+    a, b = (S.Solver(meshes, gparams(S.EULER)) for _ in range(2))
+    for s in (a, b):
+        for i, d in enumerate(insts):
+            s.set_state(i, d.state())
+    dt = a.compute_dt()
+    a.step(dt)
+    b.step_cfl()
+    for i in range(len(insts)):
+        np.testing.assert_array_equal(a.get_state(i), b.get_state(i))
+    t, steps = b.times()
+    np.testing.assert_array_equal(t, dt)
+    assert np.all(steps == 1)
+
+
 def test_ragged_riemann_batch_full_runs():
     """A ragged batch of Riemann problems (the batched workload's recipe with
     smaller meshes), each advanced to t = 0.14 with its own CFL steps."""

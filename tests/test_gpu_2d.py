@@ -172,6 +172,26 @@ def test_advection_2d():
     assert rel_err(g, o) < TOL
 
 
+def test_step_cfl_is_compute_dt_then_step():
+    """2D: one device-sized CFL step equals shw_compute_dt followed by
+    shw_step, bit for bit, on a ragged batch."""
+    sizes = [(12, 20), (70, 9), (33, 33)]
+    meshes = [S.Mesh.rect(nx, ny, 0.0, 1.0, 0.0, 1.0) for nx, ny in sizes]
+    states = [smooth_state(nx, ny, seed=k) for k, (nx, ny) in enumerate(sizes)]
+    a, b = (S.Solver(meshes, gparams()) for _ in range(2))
+    for s in (a, b):
+        for i, st in enumerate(states):
+            s.set_state(i, st)
+    dt = a.compute_dt()
+    a.step(dt)
+    b.step_cfl()
+    for i in range(len(sizes)):
+        np.testing.assert_array_equal(a.get_state(i), b.get_state(i))
+    t, steps = b.times()
+    np.testing.assert_array_equal(t, dt)
+    assert np.all(steps == 1)
+
+
 def test_compute_dt_matches_oracle():
     st = smooth_state(13, 9, 5, lx=2.0)
     s = S.Solver([S.Mesh.rect(13, 9, 0.0, 2.0, 0.0, 1.0)], gparams())
