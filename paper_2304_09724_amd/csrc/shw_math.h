@@ -179,6 +179,55 @@ SHW_HD void euler_eigen(const Re *W, double gamma, Re R[][NComp<EULER, DIM>::M],
     }
 }
 
+// The characteristic fields of the 2D Euler flux Jacobian in x at a state,
+// held as the eight numbers its eigenvectors are built from instead of the
+// 32 entries of R and L (the same matrices as euler_eigen<2, 0>): speeds
+// u - c, u, u, u + c.  char_L and char_R apply L and R in closed form.
+template <class Re>
+struct CharX {
+    Re u, v, c, ic, H, b1, b2, hq;   // hq = |u|^2 / 2
+};
+
+template <class Re>
+SHW_HD void char_x(const Re *W, double gamma, CharX<Re> &E)
+{
+    const Re ir = 1.0 / W[0];
+    E.u = W[1] * ir;
+    E.v = W[2] * ir;
+    E.hq = 0.5 * (E.u * E.u + E.v * E.v);
+    const Re p = (gamma - 1.0) * (W[3] - W[0] * E.hq);
+    E.c = sqrt(gamma * p * ir);
+    E.ic = 1.0 / E.c;
+    E.H = (W[3] + p) * ir;
+    E.b1 = (gamma - 1.0) * (E.ic * E.ic);
+    E.b2 = E.b1 * E.hq;
+}
+
+// y = L x: rows (b2 + u/c, -(b1 u + 1/c), -b1 v, b1)/2, (1 - b2, b1 u, b1 v,
+// -b1), (-v, 0, 1, 0), (b2 - u/c, -(b1 u - 1/c), -b1 v, b1)/2
+template <class Re>
+SHW_HD void char_L(const CharX<Re> &E, const Re x[4], Re y[4])
+{
+    const Re s = E.b2 * x[0] - E.b1 * (E.u * x[1] + E.v * x[2] - x[3]);
+    const Re d = E.ic * (E.u * x[0] - x[1]);
+    y[0] = 0.5 * (s + d);
+    y[1] = x[0] - s;
+    y[2] = x[2] - E.v * x[0];
+    y[3] = 0.5 * (s - d);
+}
+
+// x = R y: columns (1, u - c, v, H - u c), (1, u, v, |u|^2/2), (0, 0, 1, v),
+// (1, u + c, v, H + u c)
+template <class Re>
+SHW_HD void char_R(const CharX<Re> &E, const Re y[4], Re x[4])
+{
+    const Re s = y[0] + y[1] + y[3], d = y[3] - y[0];
+    x[0] = s;
+    x[1] = E.u * s + E.c * d;
+    x[2] = E.v * s + y[2];
+    x[3] = E.H * (y[0] + y[3]) + E.u * E.c * d + E.hq * y[1] + E.v * y[2];
+}
+
 // Physical flux in x of a point state (scalar equations: a W or W^2/2).
 template <int EQ, int DIM, class R>
 SHW_HD void phys_flux_x(const R *W, const DevParams &P, R *F)

@@ -181,14 +181,9 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
     for (int g = 0; g < 4; ++g) {
         // characteristic fields of the sweep Jacobian at the cell average
         // (read by stage 2 on characteristic waves only)
-        double Lm[M][M], Rm[M][M];
+        CharX<double> Em{};
         if constexpr (EQ == EULER) {
-            if (charpath && P.charwise) {
-                double lam[M];
-                euler_eigen<2, 0>(Wc, P.gamma, Rm, Lm, lam);
-            }
-        } else {
-            Lm[0][0] = 1.0; Rm[0][0] = 1.0;
+            if (charpath && P.charwise) char_x(Wc, P.gamma, Em);
         }
         // Stage 2 order by order; each order's jets move to the lane above at
         // once and become the GRP's series seeds there, so only one order of
@@ -219,7 +214,7 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
             }
             double lo[5][M], hi[5][M];
             if (lane >= 1 && lane <= 62 && live) {
-                stage2_order<M, EQ>(n, am, a0, ap, bm, bp, Lm, Rm, dS, scs, full, charpath, P, w,
+                stage2_order<M, EQ>(n, am, a0, ap, bm, bp, Em, dS, scs, full, charpath, P, w,
                                     lo, hi);
             } else {
 #pragma unroll

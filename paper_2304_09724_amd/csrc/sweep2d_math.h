@@ -144,28 +144,28 @@ SHW_HD Re deriv_at(const Re c[5], double eta, int n, double scale)
 // --------------------------------------------------------------------------
 template <int M, int EQ, class Re>
 SHW_HD void stage2_order(int n, const Re am[M], const Re a0[M], const Re ap[M], const Re bm[M],
-                         const Re bp[M], const Re L[M][M], const Re R[M][M], double dS,
+                         const Re bp[M], const CharX<Re> &E, double dS,
                          const double scs[5], bool full, bool charpath, const DevParams &P,
                          Re w[M][3], Re lo[5][M], Re hi[5][M])
 {
     const bool proj = EQ == EULER && charpath && P.charwise;
+    // the data in characteristic fields (Euler, characteristic path)
+    Re cm[M], c0[M], cp[M], dm[M], dp[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) { cm[c] = am[c]; c0[c] = a0[c]; cp[c] = ap[c]; dm[c] = bm[c]; dp[c] = bp[c]; }
+    if constexpr (EQ == EULER) {
+        if (proj) {
+            char_L(E, am, cm);
+            char_L(E, a0, c0);
+            char_L(E, ap, cp);
+            char_L(E, bm, dm);
+            char_L(E, bp, dp);
+        }
+    }
     Re clo[M][5], chi[M][5];
 #pragma unroll
     for (int f = 0; f < M; ++f) {
-        Re xm, x0, xp, ym, yp;
-        if (proj) {
-            xm = 0.0; x0 = 0.0; xp = 0.0; ym = 0.0; yp = 0.0;
-#pragma unroll
-            for (int c = 0; c < M; ++c) {
-                xm += L[f][c] * am[c];
-                x0 += L[f][c] * a0[c];
-                xp += L[f][c] * ap[c];
-                ym += L[f][c] * bm[c];
-                yp += L[f][c] * bp[c];
-            }
-        } else {
-            xm = am[f]; x0 = a0[f]; xp = ap[f]; ym = bm[f]; yp = bp[f];
-        }
+        const Re xm = cm[f], x0 = c0[f], xp = cp[f], ym = dm[f], yp = dp[f];
         Re q[5];
         big_quartic(xm, x0, xp, Re(dS * ym), Re(dS * yp), q);
         if (full) {
@@ -177,21 +177,22 @@ SHW_HD void stage2_order(int n, const Re am[M], const Re a0[M], const Re ap[M], 
 #pragma unroll
     for (int a = 0; a < 5; ++a) {
         if (a + n > 4) continue;
+        Re l[M], h[M];
+#pragma unroll
+        for (int f = 0; f < M; ++f) { l[f] = clo[f][a]; h[f] = chi[f][a]; }
+        if constexpr (EQ == EULER) {
+            if (proj) {
+                Re tl[M], th[M];
+                char_R(E, l, tl);
+                char_R(E, h, th);
+#pragma unroll
+                for (int c = 0; c < M; ++c) { l[c] = tl[c]; h[c] = th[c]; }
+            }
+        }
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-            Re l = 0.0, h = 0.0;
-            if (proj) {
-#pragma unroll
-                for (int f = 0; f < M; ++f) {
-                    l += R[c][f] * clo[f][a];
-                    h += R[c][f] * chi[f][a];
-                }
-            } else {
-                l = clo[c][a];
-                h = chi[c][a];
-            }
-            lo[a][c] = l * scs[a];
-            hi[a][c] = h * scs[a];
+            lo[a][c] = l[c] * scs[a];
+            hi[a][c] = h[c] * scs[a];
         }
     }
 }
@@ -253,7 +254,9 @@ SHW_HD void ck2d_adv(const R s[5][5], double as, double at, R wt[5])
 // --------------------------------------------------------------------------
 template <int M, int EQ, class Re>
 struct Leading2D {
-    Re Ws[M], R[M][M], L[M][M], lam[M], scale;
+    Re Ws[M], scale;
+    CharX<Re> E;     // Euler: characteristic fields at Ws (speeds u-c, u, u, u+c)
+    Re lam0;         // advection: the speed
 };
 
 template <int M, int EQ, class Re>
@@ -262,16 +265,12 @@ SHW_HD void grp2d_leading(const Re JL[M], const Re JR[M], const DevParams &P, do
 {
     if constexpr (EQ == EULER) {
         hllc_state<2>(JL, JR, P.gamma, G.Ws);
-        euler_eigen<2, 0>(G.Ws, P.gamma, G.R, G.L, G.lam);
-        G.scale = 0.0;
-#pragma unroll
-        for (int f = 0; f < M; ++f) G.scale = fmax(G.scale, fabs(G.lam[f]));
+        char_x(G.Ws, P.gamma, G.E);
+        G.scale = fabs(G.E.u) + G.E.c;
     } else {
-        G.lam[0] = as;
+        G.lam0 = as;
         G.scale = fabs(as);
-        G.R[0][0] = 1.0;
-        G.L[0][0] = 1.0;
-        G.Ws[0] = upwind(G.lam[0], G.scale, JL[0], JR[0]);
+        G.Ws[0] = upwind(G.lam0, G.scale, JL[0], JR[0]);
     }
 }
 
@@ -280,26 +279,17 @@ SHW_HD void grp2d_seed(const Re JL[M], const Re JR[M], const Leading2D<M, EQ, Re
                        double factor, Re out[M])
 {
     if constexpr (EQ == EULER) {
-        Re ch[M];
+        Re l[M], r[M], ch[M];
+        char_L(G.E, JL, l);
+        char_L(G.E, JR, r);
+        const Re lam[M] = {G.E.u - G.E.c, G.E.u, G.E.u, G.E.u + G.E.c};
 #pragma unroll
-        for (int f = 0; f < M; ++f) {
-            Re l = 0.0, r = 0.0;
+        for (int f = 0; f < M; ++f) ch[f] = upwind(lam[f], G.scale, l[f], r[f]);
+        char_R(G.E, ch, out);
 #pragma unroll
-            for (int c = 0; c < M; ++c) {
-                l += G.L[f][c] * JL[c];
-                r += G.L[f][c] * JR[c];
-            }
-            ch[f] = upwind(G.lam[f], G.scale, l, r);
-        }
-#pragma unroll
-        for (int c = 0; c < M; ++c) {
-            Re d = 0.0;
-#pragma unroll
-            for (int f = 0; f < M; ++f) d += G.R[c][f] * ch[f];
-            out[c] = d * factor;
-        }
+        for (int c = 0; c < M; ++c) out[c] *= factor;
     } else {
-        out[0] = upwind(G.lam[0], G.scale, JL[0], JR[0]) * factor;
+        out[0] = upwind(G.lam0, G.scale, JL[0], JR[0]) * factor;
     }
 }
 

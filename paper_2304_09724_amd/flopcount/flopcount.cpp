@@ -111,8 +111,8 @@ static void euler2d(bool full, const char *name)
         stage1<M, EULER>(W, V, Y, Z, 0.01, full, full, P, PW, PV);
         for (int gn = 0; gn < 4; ++gn) {
             const double eta = gn == 0 ? -0.5 : gn == 1 ? -LOB_H : gn == 2 ? LOB_H : 0.5;
-            Cnt Lm[M][M], Rm[M][M], lam[M];
-            euler_eigen<2, 0>(W[1], P.gamma, Rm, Lm, lam);
+            CharX<Cnt> Em;
+            char_x(W[1], P.gamma, Em);
             Cnt w[M][3], lo[5][M], hi[5][M];
             Cnt JL[15][M], JR[15][M];
             for (int n = 0; n <= 4; ++n) {
@@ -121,7 +121,7 @@ static void euler2d(bool full, const char *name)
                     a0[c] = deriv_at(PW[c], eta, n, sc[n]);
                     b0[c] = deriv_at(PV[c], eta, n, sc[n]);
                 }
-                stage2_order<M, EULER>(n, a0, a0, a0, b0, b0, Lm, Rm, 0.01, sc, full, full, P, w, lo, hi);
+                stage2_order<M, EULER>(n, a0, a0, a0, b0, b0, Em, 0.01, sc, full, full, P, w, lo, hi);
                 for (int a = 0; a + n <= 4; ++a)
                     for (int c = 0; c < M; ++c) {
                         JL[jidx(a, n)][c] = hi[a][c];
