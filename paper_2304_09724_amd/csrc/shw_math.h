@@ -179,6 +179,51 @@ SHW_HD void euler_eigen(const Re *W, double gamma, Re R[][NComp<EULER, DIM>::M],
     }
 }
 
+// The characteristic fields of the 1D Euler flux Jacobian at a state, held
+// as the seven numbers its eigenvectors are built from instead of the 18
+// entries of R and L (the matrices of euler_eigen<1, 0>): speeds u - c, u,
+// u + c.  char1_L and char1_R apply L and R in closed form.
+template <class Re>
+struct Char1 {
+    Re u, c, ic, H, b1, b2, hq;      // hq = u^2 / 2
+};
+
+template <class Re>
+SHW_HD void char_1d(const Re *W, double gamma, Char1<Re> &E)
+{
+    const Re ir = 1.0 / W[0];
+    E.u = W[1] * ir;
+    E.hq = 0.5 * E.u * E.u;
+    const Re p = (gamma - 1.0) * (W[2] - W[0] * E.hq);
+    E.c = sqrt(gamma * p * ir);
+    E.ic = 1.0 / E.c;
+    E.H = (W[2] + p) * ir;
+    E.b1 = (gamma - 1.0) * (E.ic * E.ic);
+    E.b2 = E.b1 * E.hq;
+}
+
+// y = L x: rows (b2 + u/c, -(b1 u + 1/c), b1)/2, (1 - b2, b1 u, -b1),
+// (b2 - u/c, -(b1 u - 1/c), b1)/2
+template <class Re>
+SHW_HD void char1_L(const Char1<Re> &E, const Re x[3], Re y[3])
+{
+    const Re s = E.b2 * x[0] - E.b1 * (E.u * x[1] - x[2]);
+    const Re d = E.ic * (E.u * x[0] - x[1]);
+    y[0] = 0.5 * (s + d);
+    y[1] = x[0] - s;
+    y[2] = 0.5 * (s - d);
+}
+
+// x = R y: columns (1, u - c, H - u c), (1, u, u^2/2), (1, u + c, H + u c)
+template <class Re>
+SHW_HD void char1_R(const Char1<Re> &E, const Re y[3], Re x[3])
+{
+    const Re s = y[0] + y[1] + y[2], d = y[2] - y[0];
+    x[0] = s;
+    x[1] = E.u * s + E.c * d;
+    x[2] = E.H * (y[0] + y[2]) + E.u * E.c * d + E.hq * y[1];
+}
+
 // The characteristic fields of the 2D Euler flux Jacobian in x at a state,
 // held as the eight numbers its eigenvectors are built from instead of the
 // 32 entries of R and L (the same matrices as euler_eigen<2, 0>): speeds

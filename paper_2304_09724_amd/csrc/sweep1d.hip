@@ -263,10 +263,11 @@ __device__ inline void work_priority(double work, double share)
     }
 }
 
-// Two waves per SIMD (at most 256 registers a lane) is the occupancy the
-// kernel is written for: one wave alone cannot hide its FP64 latencies.
+// Occupancy: at least two waves per SIMD (at most 256 registers a lane), one
+// wave alone cannot hide its FP64 latencies; the plain Euler instance fits a
+// third (168 registers).
 template <int EQ, int NB, bool LRN, bool GUARD>
-__global__ void __launch_bounds__(NB) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__(NB) __attribute__((amdgpu_waves_per_eu(EQ == EULER && !LRN && !GUARD ? 3 : 2)))
 loop1d_kernel(Loop1D Lp, DevParams P)
 {
     constexpr int M = NComp<EQ, 1>::M;

@@ -56,42 +56,39 @@ SHW_HD void recon_cell(const Re Wm[M], const Re W0[M], const Re Wp[M], const Re 
     sc[0] = 1.0; sc[1] = idx; sc[2] = idx * idx; sc[3] = sc[2] * idx; sc[4] = sc[2] * sc[2];
     if constexpr (EQ == EULER) {
         if (charpath && P.charwise) {
-            Re R[M][M], L[M][M], lam[M];
-            euler_eigen<1, 0>(W0, P.gamma, R, L, lam);
+            Char1<Re> E;
+            char_1d(W0, P.gamma, E);
+            Re cm[M], c0[M], cp[M], dm[M], dp[M];
+            char1_L(E, Wm, cm);
+            char1_L(E, W0, c0);
+            char1_L(E, Wp, cp);
+            char1_L(E, Vm, dm);
+            char1_L(E, Vp, dp);
             Re clo[M][5], chi[M][5];
 #pragma unroll
             for (int s = 0; s < M; ++s) {
-                Re am = 0.0, a0 = 0.0, ap = 0.0, bm = 0.0, bp = 0.0;
-#pragma unroll
-                for (int c = 0; c < M; ++c) {
-                    am += L[s][c] * Wm[c];
-                    a0 += L[s][c] * W0[c];
-                    ap += L[s][c] * Wp[c];
-                    bm += L[s][c] * Vm[c];
-                    bp += L[s][c] * Vp[c];
-                }
                 Re q[5];
-                big_quartic(am, a0, ap, Re(dx * bm), Re(dx * bp), q);
+                big_quartic(cm[s], c0[s], cp[s], Re(dx * dm[s]), Re(dx * dp[s]), q);
                 if (full) {
                     Re w[3];
-                    nonlinear_weights(q, am, a0, ap, P, w);
-                    combine(q, am, a0, ap, w, P);
+                    nonlinear_weights(q, cm[s], c0[s], cp[s], P, w);
+                    combine(q, cm[s], c0[s], cp[s], w, P);
                 }
                 edge_derivs(q, clo[s], chi[s]);
             }
 #pragma unroll
-            for (int a = 0; a < 5; ++a)
+            for (int a = 0; a < 5; ++a) {
+                const Re yl[M] = {clo[0][a], clo[1][a], clo[2][a]};
+                const Re yh[M] = {chi[0][a], chi[1][a], chi[2][a]};
+                Re l[M], h[M];
+                char1_R(E, yl, l);
+                char1_R(E, yh, h);
 #pragma unroll
                 for (int c = 0; c < M; ++c) {
-                    Re l = 0.0, h = 0.0;
-#pragma unroll
-                    for (int s = 0; s < M; ++s) {
-                        l += R[c][s] * clo[s][a];
-                        h += R[c][s] * chi[s][a];
-                    }
-                    lo[a][c] = l * sc[a];
-                    hi[a][c] = h * sc[a];
+                    lo[a][c] = l[c] * sc[a];
+                    hi[a][c] = h[c] * sc[a];
                 }
+            }
             return;
         }
     }
@@ -191,35 +188,25 @@ SHW_HD void face1d(const Re JL[5][M], const Re JR[5][M], double dt, const DevPar
     Re w[M][5][5];
     // leading term (sec. 2.1.1) and the derivative Riemann problems (eq. (lineq))
     if constexpr (EQ == EULER) {
-        Re Ws[M], R[M][M], L[M][M], lam[M];
+        Re Ws[M];
+        Char1<Re> E;
         hllc_state<1>(JL[0], JR[0], P.gamma, Ws);
-        euler_eigen<1, 0>(Ws, P.gamma, R, L, lam);
-        Re scale = 0.0;
-#pragma unroll
-        for (int s = 0; s < M; ++s) scale = fmax(scale, fabs(lam[s]));
+        char_1d(Ws, P.gamma, E);
+        const Re lam[M] = {E.u - E.c, E.u, E.u + E.c};
+        const Re scale = fabs(E.u) + E.c;
 #pragma unroll
         for (int c = 0; c < M; ++c) w[c][0][0] = Ws[c];
         const double inv_fact[5] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
 #pragma unroll
         for (int a = 1; a < 5; ++a) {
-            Re ch[M];
+            Re l[M], r[M], ch[M], d[M];
+            char1_L(E, JL[a], l);
+            char1_L(E, JR[a], r);
 #pragma unroll
-            for (int s = 0; s < M; ++s) {
-                Re l = 0.0, r = 0.0;
+            for (int s = 0; s < M; ++s) ch[s] = upwind(lam[s], scale, l[s], r[s]);
+            char1_R(E, ch, d);
 #pragma unroll
-                for (int c = 0; c < M; ++c) {
-                    l += L[s][c] * JL[a][c];
-                    r += L[s][c] * JR[a][c];
-                }
-                ch[s] = upwind(lam[s], scale, l, r);
-            }
-#pragma unroll
-            for (int c = 0; c < M; ++c) {
-                Re d = 0.0;
-#pragma unroll
-                for (int s = 0; s < M; ++s) d += R[c][s] * ch[s];
-                w[c][a][0] = d * inv_fact[a];
-            }
+            for (int c = 0; c < M; ++c) w[c][a][0] = d[c] * inv_fact[a];
         }
     } else {
         Re lam;
