@@ -173,7 +173,10 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
     const double node[4] = {-0.5, -LOB_H, LOB_H, 0.5};
     const double nw[4] = {LOB_W0, LOB_W1, LOB_W1, LOB_W0};
 
-    double Fh[M], We[4][M];
+    // the faces' values at t_{n+1} wait in LDS for the update (NB + 1 slots:
+    // the update reads its own lane's and the next lane's)
+    __shared__ double s_we[4][M][NB + 1];
+    double Fh[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) Fh[c] = 0.0;
     const bool face = lane >= 2 && lane <= 62 && s >= 0 && s <= ns;
@@ -249,20 +252,24 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
 #pragma unroll
             for (int c = 0; c < M; ++c) {
                 Fh[c] += nw[g] * Fg[c];
-                We[g][c] = Wg[c];
+                s_we[g][c][threadIdx.x] = Wg[c];
             }
         } else {
 #pragma unroll
-            for (int c = 0; c < M; ++c) We[g][c] = 0.0;
+            for (int c = 0; c < M; ++c) s_we[g][c][threadIdx.x] = 0.0;
         }
     }
     // ---- update (this lane's cell; upper interface from lane + 1) ----------
-    double Fu[M], Wu[4][M];
+    __syncthreads();            // every lane's face values are in s_we
+    double Fu[M], We[4][M], Wu[4][M];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
         Fu[c] = from_lane_above(Fh[c]);
 #pragma unroll
-        for (int g = 0; g < 4; ++g) Wu[g][c] = from_lane_above(We[g][c]);
+        for (int g = 0; g < 4; ++g) {
+            We[g][c] = s_we[g][c][threadIdx.x];
+            Wu[g][c] = s_we[g][c][threadIdx.x + 1];
+        }
     }
     if (!(lane >= 2 && lane <= 61 && s >= 0 && s < ns)) return;
     const int i = DIR == 0 ? s : t, j = DIR == 0 ? t : s;
