@@ -100,12 +100,27 @@ __device__ __forceinline__ int find_instance(const int *__restrict__ off, int n,
     return lo;
 }
 
+// Workgroups go to the eight XCDs in turn (workgroup b to XCD b mod 8), each
+// XCD with its own L2.  Tile numbers are dealt so that every XCD takes a
+// contiguous run of them (XCD x the x-th of eight near-equal runs, in order):
+// neighbouring tiles, which share cache lines (a y-sweep's adjacent columns,
+// an x-sweep's transverse stencil rows), then fill one L2 instead of eight.
+// A bijection of [0, nblocks) onto itself for any nblocks.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks)
+{
+    constexpr int XCDS = 8;
+    const int q = nblocks / XCDS, r = nblocks % XCDS;
+    const int x = b % XCDS;
+    return x * q + min(x, r) + b / XCDS;
+}
+
 template <int EQ, int DIR, int L>
 __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
 {
     constexpr int NB = 64 * L;
     constexpr int M = NComp<EQ, 2>::M;
-    const int inst = find_instance(S.tile_off[DIR], S.n_inst, blockIdx.x);
+    const int bid = xcd_tile(blockIdx.x, gridDim.x);
+    const int inst = find_instance(S.tile_off[DIR], S.n_inst, bid);
     const double dt = S.dt[inst];
     if (!(dt > 0.0)) return;
     const Inst2D d = S.inst[inst];
@@ -113,7 +128,7 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
     const double dS = DIR == 0 ? d.dx : d.dy, dT = DIR == 0 ? d.dy : d.dx;
     const double as = DIR == 0 ? P.adv_a : P.adv_b, at = DIR == 0 ? P.adv_b : P.adv_a;
     const int tiles_s = (ns + CHUNK - 1) / CHUNK;
-    const int tile = blockIdx.x - S.tile_off[DIR][inst];
+    const int tile = bid - S.tile_off[DIR][inst];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int t = (tile / tiles_s) * L + wave;
     if (t >= nt) return;
@@ -333,13 +348,14 @@ __global__ void __launch_bounds__(64 * L) gate2d_kernel(Step2D S, DevParams P)
 {
     constexpr int M = 4;
     __shared__ u32x4 s_gate[GATE_LDS_WORDS];
-    const int inst = find_instance(S.tile_off[0], S.n_inst, blockIdx.x);
+    const int bid = xcd_tile(blockIdx.x, gridDim.x);
+    const int inst = find_instance(S.tile_off[0], S.n_inst, bid);
     if (!(S.dt[inst] > 0.0)) return;              // the whole block: instance idle
     gate_to_lds(S.gate, s_gate, threadIdx.x, 64 * L);
     __syncthreads();
     const Inst2D d = S.inst[inst];
     const int tiles_s = (d.nx + CHUNK - 1) / CHUNK;
-    const int tile = blockIdx.x - S.tile_off[0][inst];
+    const int tile = bid - S.tile_off[0][inst];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int t = (tile / tiles_s) * L + wave;
     if (t >= d.ny) return;                        // the whole wave: past the last row
