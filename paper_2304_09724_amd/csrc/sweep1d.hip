@@ -65,8 +65,7 @@ template <int EQ, int NB, bool LRN, bool GUARD>
 __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__restrict__ src,
                                                double *__restrict__ dst, double dt,
                                                const DevParams &P,
-                                               uint8_t *__restrict__ flags, const u32x4 *gate,
-                                               float gate_logit_min, int gate_since,
+                                               const uint8_t *__restrict__ flags, int gate_since,
                                                double *spd_out, double *__restrict__ faces)
 {
     constexpr int M = NComp<EQ, 1>::M;
@@ -89,27 +88,17 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
         bool full = P.weights == W_NONLINEAR;
         if (P.weights == W_GATED) full = flags[d.cell_off + s0] != 0;
         if constexpr (LRN) {
-            {
-                if (gate_since == 0) {
-                    // the whole wave evaluates the network for its 64 cells;
-                    // the owners keep the decision for the steps until the next
-                    float f[GATE_NF];
-                    gate_features1d(Wm, W0, Wp, Vm, Vp, d.dx, P.gamma, f);
-                    full = gate_wave_logit(f, gate_lane_lds(gate, lane)) >= gate_logit_min;
-                    if (lane >= 1 && lane <= CHUNK && j >= 0 && j < n)
-                        flags[d.cell_off + j] = (uint8_t)full;
-                } else {
-                    // s steps after the gate ran, a cell can need the nonlinear
-                    // weights only if a cell flagged then lies within 2s cells:
-                    // its reconstruction reads its neighbours, and each step
-                    // updates a cell from the reconstructions next to it
-                    const int reach = 2 * gate_since;
-                    unsigned any = 0;
-                    for (int o = -reach; o <= reach; ++o)
-                        any |= flags[d.cell_off + flag_cell(jl + o, n, d.bc_lo, d.bc_hi)];
-                    full = any != 0;
-                }
-            }
+            // the decisions of the last gate pass (gate_pass, run at this
+            // step or gate_since steps ago): s steps after it, a cell can need
+            // the nonlinear weights only if a cell flagged then lies within 2s
+            // cells (its reconstruction reads its neighbours, and each step
+            // updates a cell from the reconstructions next to it); a ghost
+            // cell stands for the cell it copies
+            const int reach = 2 * gate_since;
+            unsigned any = 0;
+            for (int o = -reach; o <= reach; ++o)
+                any |= flags[d.cell_off + flag_cell(jl + o, n, d.bc_lo, d.bc_hi)];
+            full = any != 0;
         }
         double lo[5][M], hi[5][M];
         // one reconstruction path per wave: characteristic if any lane needs
@@ -161,6 +150,33 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
     spd = wave_max(spd);
     if (lane == 0) spd_out[wave] = spd;
     return bad;
+}
+
+// The learned gate's pass over an instance (every gate_every steps): each
+// wave evaluates the network for the 64 cells of a chunk (all lanes take part
+// in the matrix instructions) and the owners store the decisions in the
+// per-cell flags, which the sweeps then read.  A pass of its own keeps the
+// network's registers out of the sweep's.
+template <int NB>
+__device__ void gate_pass(const Inst1D &d, const double *__restrict__ src, const DevParams &P,
+                          uint8_t *__restrict__ flags, const u32x4 *gate, float gate_logit_min)
+{
+    constexpr int M = 3;
+    const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
+    const int n = d.n;
+    const int nchunk = (n + CHUNK - 1) / CHUNK;
+    for (int ch = wave; ch < nchunk; ch += NB / WAVE) {
+        const int j = ch * CHUNK + lane - 1;
+        const int jl = j <= n ? j : n;
+        double Wm[M], Vm[M], W0[M], V0[M], Wp[M], Vp[M];
+        load_cell<EULER, M>(src, n, jl - 1, d.bc_lo, d.bc_hi, Wm, Vm);
+        load_cell<EULER, M>(src, n, jl, d.bc_lo, d.bc_hi, W0, V0);
+        load_cell<EULER, M>(src, n, jl + 1, d.bc_lo, d.bc_hi, Wp, Vp);
+        float f[GATE_NF];
+        gate_features1d(Wm, W0, Wp, Vm, Vp, d.dx, P.gamma, f);
+        const bool full = gate_wave_logit(f, gate_lane_lds(gate, lane)) >= gate_logit_min;
+        if (lane >= 1 && lane <= CHUNK && j >= 0 && j < n) flags[d.cell_off + j] = (uint8_t)full;
+    }
 }
 
 // Positivity safeguard (an addition to the paper's scheme, which has no
@@ -264,10 +280,10 @@ __device__ inline void work_priority(double work, double share)
 }
 
 // Occupancy: at least two waves per SIMD (at most 256 registers a lane), one
-// wave alone cannot hide its FP64 latencies; the plain Euler instance fits a
-// third (168 registers).
+// wave alone cannot hide its FP64 latencies; the Euler instances without the
+// safeguard fit a third (168 registers).
 template <int EQ, int NB, bool LRN, bool GUARD>
-__global__ void __launch_bounds__(NB) __attribute__((amdgpu_waves_per_eu(EQ == EULER && !LRN && !GUARD ? 3 : 2)))
+__global__ void __launch_bounds__(NB) __attribute__((amdgpu_waves_per_eu(EQ == EULER && !GUARD ? 3 : 2)))
 loop1d_kernel(Loop1D Lp, DevParams P)
 {
     constexpr int M = NComp<EQ, 1>::M;
@@ -338,9 +354,14 @@ loop1d_kernel(Loop1D Lp, DevParams P)
             // steps of the instance; steps are separated by block barriers, so
             // the decisions one wave stores are seen by the other waves
             gate_since = (k == 0 || (st.steps + k) % Lp.gate_every == 0) ? 0 : gate_since + 1;
+            if constexpr (LRN) {
+                if (gate_since == 0) {
+                    gate_pass<NB>(d, A, P, Lp.flags, s_gate, Lp.gate_logit_min);
+                    __syncthreads();        // every decision stored before the sweep reads them
+                }
+            }
             double *faces = GUARD ? Lp.faces + 2LL * M * (d.cell_off + i) : nullptr;
-            const bool bad = sweep_instance<EQ, NB, LRN, GUARD>(d, A, B, dt, P, Lp.flags, s_gate,
-                                                                Lp.gate_logit_min, gate_since,
+            const bool bad = sweep_instance<EQ, NB, LRN, GUARD>(d, A, B, dt, P, Lp.flags, gate_since,
                                                                 s_spd[buf ^ 1], faces);
             // a full barrier (with workgroup fences) orders the speeds in LDS and
             // the gate's stored decisions for the next step

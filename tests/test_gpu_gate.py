@@ -339,8 +339,10 @@ def test_trained_gate_keeps_the_2d_solution(trained, case):
 
 def test_gate_speeds_up_2d_runs(trained):
     """The point of the gate: on a 2D problem with shocks and smooth regions
-    (four-quadrant, 512^2, 20 steps) the learned gate runs at least 1.1x the
-    plain throughput, best of three each."""
+    (four-quadrant, 512^2, 20 steps) the learned gate runs faster than the
+    plain scheme by at least 5%, best of three each (1.12x measured; 1.25x
+    before the plain 2D sweep's characteristic fields went to closed form,
+    which shrank the share of the work the gate saves)."""
     import time
     params = trained[2]
     n = 512
@@ -368,4 +370,4 @@ def test_gate_speeds_up_2d_runs(trained):
     t_plain = best(S.Params.make(eq=S.EULER))
     t_gated = best(S.Params.make(eq=S.EULER, weights=S.W_LEARNED, gate_threshold=0.05))
     print(f"four-quadrant 512^2, 20 steps: gated {t_plain / t_gated:.3f}x plain")
-    assert t_plain / t_gated >= 1.1, (t_plain, t_gated)
+    assert t_plain / t_gated >= 1.05, (t_plain, t_gated)
