@@ -280,10 +280,10 @@ __device__ inline void work_priority(double work, double share)
 }
 
 // Occupancy: at least two waves per SIMD (at most 256 registers a lane), one
-// wave alone cannot hide its FP64 latencies; the Euler instances without the
-// safeguard fit a third (168 registers).
+// wave alone cannot hide its FP64 latencies; the Euler instances fit a third
+// (168 registers, a few of them spilled).
 template <int EQ, int NB, bool LRN, bool GUARD>
-__global__ void __launch_bounds__(NB) __attribute__((amdgpu_waves_per_eu(EQ == EULER && !GUARD ? 3 : 2)))
+__global__ void __launch_bounds__(NB) __attribute__((amdgpu_waves_per_eu(EQ == EULER ? 3 : 2)))
 loop1d_kernel(Loop1D Lp, DevParams P)
 {
     constexpr int M = NComp<EQ, 1>::M;
