@@ -127,12 +127,18 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
     const int ns = DIR == 0 ? d.nx : d.ny, nt = DIR == 0 ? d.ny : d.nx;
     const double dS = DIR == 0 ? d.dx : d.dy, dT = DIR == 0 ? d.dy : d.dx;
     const double as = DIR == 0 ? P.adv_a : P.adv_b, at = DIR == 0 ? P.adv_b : P.adv_a;
-    const int tiles_s = (ns + CHUNK - 1) / CHUNK;
+    const int tiles_s = (ns + CHUNK - 1) / CHUNK, tiles_t = (nt + L - 1) / L;
     const int tile = bid - S.tile_off[DIR][inst];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
-    const int t = (tile / tiles_s) * L + wave;
+    // consecutive tiles: along the lines for the x-sweep (a row band at a
+    // time), across them for the y-sweep (a band of rows over all columns),
+    // so tiles running together read the same cache lines (a line holds 16
+    // neighbouring columns of a row)
+    const int tile_s = DIR == 0 ? tile % tiles_s : tile / tiles_t;
+    const int tile_t = DIR == 0 ? tile / tiles_s : tile % tiles_t;
+    const int t = tile_t * L + wave;
     if (t >= nt) return;
-    const int s = (tile % tiles_s) * CHUNK + lane - 2;
+    const int s = tile_s * CHUNK + lane - 2;
     const bool live = s <= ns + 1;
     const int par = S.parity[inst];
     const double *src = (par ? S.alt : S.state) + d.off;
