@@ -63,7 +63,7 @@ class Config:
     adv_b: float = 0.0
     eps: float = 1e-6
     lin_w: tuple = (0.994, 0.003, 0.003)
-    positivity: bool = False        # 1D Euler safeguard (not in the paper)
+    positivity: bool = False        # Euler safeguard (not in the paper)
 
     def c(self) -> _Cfg:
         s = _Cfg()

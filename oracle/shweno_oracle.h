@@ -47,8 +47,9 @@ typedef struct {
     double adv_b;      /* advection speed in y */
     double eps;        /* regulariser of the nonlinear weights */
     double lin_w[3];   /* linear weights: quartic, left linear, right linear */
-    int positivity;    /* 1D Euler: 1 = the positivity safeguard of orc_step1d
-                          (an addition, not in the paper; 0 = the paper's scheme) */
+    int positivity;    /* Euler: 1 = the positivity safeguard of orc_step1d and
+                          orc_step2d (an addition, not in the paper; 0 = the
+                          paper's scheme) */
 } orc_cfg;
 
 /* number of conservative components of an equation in dimension dim */
@@ -115,7 +116,7 @@ double orc_dt2d(const orc_cfg *cfg, int nx, int ny, double dx, double dy,
 /* One step of size dt.  flags (may be NULL unless cfg->weights is GATED):
  * one byte per cell, non-zero = full nonlinear reconstruction.  Returns 0,
  * or 1 if the new state has a non-finite value, rho<=0 or p<=0.
- * With cfg->positivity (1D Euler), the faces of cells whose update would be
+ * With cfg->positivity (Euler), the faces of cells whose update would be
  * non-physical take the first-order HLLE flux of the two averages at t_n
  * before the step is judged; see step.c. */
 int orc_step1d(const orc_cfg *cfg, int n, double dx, double dt,

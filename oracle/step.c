@@ -523,6 +523,72 @@ static int comp_swap(const orc_cfg *cfg, int c)
     return c == 1 ? 2 : (c == 2 ? 1 : c);
 }
 
+/* The 2D positivity safeguard (cfg->positivity; an addition, as in 1D): a
+ * cell is troubled when its update from the face data would be non-physical;
+ * every x- and y-face next to a troubled cell takes the first-order HLLE flux
+ * of the two cell averages at t_n (ghosts by the boundary conditions; a
+ * y-face in the frame with x and y exchanged, in which its arrays are kept),
+ * and the HLLE state at x/t = 0 stands for the face value at t_{n+1} at all
+ * four edge nodes.  Fh/Wx: x-faces; Gt/Wyt: y-faces, transposed frame. */
+static void first_order_faces2d(const orc_cfg *cfg, int nx, int ny, double dx, double dy,
+                                double dt, const double *in, double *Fh, double *Wx,
+                                double *Gt, double *Wyt)
+{
+    const int m = 4;
+    size_t plane = (size_t)nx * ny;
+    unsigned char *trouble = malloc(plane);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            double Wn[4];
+            size_t o = (size_t)j * nx + i;
+            for (int c = 0; c < m; ++c) {
+                int cs = comp_swap(cfg, c);
+                Wn[c] = in[c * plane + o]
+                      - dt / dx * (Fh[((size_t)j * (nx + 1) + i + 1) * m + c]
+                                   - Fh[((size_t)j * (nx + 1) + i) * m + c])
+                      - dt / dy * (Gt[((size_t)i * (ny + 1) + j + 1) * m + cs]
+                                   - Gt[((size_t)i * (ny + 1) + j) * m + cs]);
+            }
+            trouble[o] = (unsigned char)nonphysical(cfg, 2, Wn);
+        }
+    /* x-faces: face f of row j between cells f-1 and f */
+    for (int j = 0; j < ny; ++j)
+        for (int f = 0; f <= nx; ++f) {
+            int l = source_index(cfg->bc[0], nx, f - 1), r = source_index(cfg->bc[1], nx, f);
+            if (!trouble[(size_t)j * nx + l] && !trouble[(size_t)j * nx + r]) continue;
+            double QL[4][4], QR[4][4], F[4], Ws[4];
+            orc_cell2d(cfg, nx, ny, in, f - 1, j, QL);
+            orc_cell2d(cfg, nx, ny, in, f, j, QR);
+            orc_hlle(cfg->gamma, 2, QL[0], QR[0], F, Ws);
+            for (int c = 0; c < m; ++c) {
+                Fh[((size_t)j * (nx + 1) + f) * m + c] = F[c];
+                for (int g = 0; g < 4; ++g)
+                    Wx[(((size_t)j * (nx + 1) + f) * 4 + g) * m + c] = Ws[c];
+            }
+        }
+    /* y-faces: face f of column i between cells f-1 and f, in the frame with
+     * x and y exchanged (momenta swapped) */
+    for (int i = 0; i < nx; ++i)
+        for (int f = 0; f <= ny; ++f) {
+            int l = source_index(cfg->bc[2], ny, f - 1), r = source_index(cfg->bc[3], ny, f);
+            if (!trouble[(size_t)l * nx + i] && !trouble[(size_t)r * nx + i]) continue;
+            double QL[4][4], QR[4][4], WL[4], WR[4], F[4], Ws[4];
+            orc_cell2d(cfg, nx, ny, in, i, f - 1, QL);
+            orc_cell2d(cfg, nx, ny, in, i, f, QR);
+            for (int c = 0; c < m; ++c) {
+                WL[comp_swap(cfg, c)] = QL[0][c];
+                WR[comp_swap(cfg, c)] = QR[0][c];
+            }
+            orc_hlle(cfg->gamma, 2, WL, WR, F, Ws);
+            for (int c = 0; c < m; ++c) {
+                Gt[((size_t)i * (ny + 1) + f) * m + c] = F[c];
+                for (int g = 0; g < 4; ++g)
+                    Wyt[(((size_t)i * (ny + 1) + f) * 4 + g) * m + c] = Ws[c];
+            }
+        }
+    free(trouble);
+}
+
 int orc_step2d(const orc_cfg *cfg, int nx, int ny, double dx, double dy,
                double dt, const double *in, double *out,
                const unsigned char *flags)
@@ -555,6 +621,8 @@ int orc_step2d(const orc_cfg *cfg, int nx, int ny, double dx, double dy,
     double *Gt = malloc(sizeof(double) * (size_t)nx * (ny + 1) * m);
     double *Wyt = malloc(sizeof(double) * (size_t)nx * (ny + 1) * 4 * m);
     xsweep(&ct, ny, nx, dy, dx, dt, tst, tfl, Gt, Wyt);
+    if (cfg->positivity && cfg->eq == ORC_EULER)
+        first_order_faces2d(cfg, nx, ny, dx, dy, dt, in, Fh, Wx, Gt, Wyt);
     /* update (Step 5) */
     int bad = 0;
 #define FH(j, f, c) Fh[((size_t)(j) * (nx + 1) + (f)) * m + (c)]
