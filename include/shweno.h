@@ -89,15 +89,16 @@ typedef struct {
  * takes the characteristic path if any of its cells needs the nonlinear
  * weights; its linear-weight cells then get the big quartic of their
  * characteristic fields, equal to the componentwise one up to rounding.
- * positivity (0 or 1; Euler, 1D only): 0 is the paper's scheme, which has no
- * limiter; 1 adds a safeguard that is not in the paper: in a step that leaves
- * a non-physical average (non-finite, rho <= 0 or p <= 0), every face next to
- * such a cell takes the first-order HLLE flux of the two averages at t_n
- * (Einfeldt's wave-speed bounds), its state at x/t = 0 standing for the face
- * value at t_{n+1}; the cells on both sides of those faces are updated again,
- * so the step stays conservative, and only a cell still non-physical then
- * stops its instance.  Steps that need no repair are unchanged bit for bit;
- * the workspace grows by 48 bytes and 1 byte per cell. */
+ * positivity (0 or 1; Euler, 1D and 2D): 0 is the paper's scheme, which has
+ * no limiter; 1 adds a safeguard that is not in the paper: in a step that
+ * leaves a non-physical average (non-finite, rho <= 0 or p <= 0), every face
+ * (2D: x- and y-face) next to such a cell takes the first-order HLLE flux of
+ * the two averages at t_n (Einfeldt's wave-speed bounds), its state at x/t =
+ * 0 standing for the face value(s) at t_{n+1}; the cells on both sides of
+ * those faces are updated again, so the step stays conservative, and only a
+ * cell still non-physical then stops its instance.  Steps that need no
+ * repair are unchanged bit for bit; the workspace grows by 48 bytes (1D) or
+ * 320 bytes (2D) and 1 byte per cell. */
 typedef struct {
     int eq;
     int charwise;
@@ -120,8 +121,8 @@ size_t shw_state_doubles(const shw_mesh *mesh, const shw_params *params);
 
 /* Bytes of device workspace shw_create needs for this batch, 0 if invalid
  * (meshes of different dimensions, Burgers outside 1D, the learned gate
- * for another equation than Euler, the positivity safeguard outside 1D
- * Euler, or an invalid mesh or parameter set). */
+ * for another equation than Euler, the positivity safeguard for another
+ * equation than Euler, or an invalid mesh or parameter set). */
 size_t shw_workspace_bytes(const shw_mesh *meshes, int n_inst, const shw_params *params);
 
 /* Create a context for n_inst instances (all with the same dim and params).

@@ -58,8 +58,8 @@ class Params(ctypes.Structure):
     def make(cls, eq=EULER, charwise=True, weights=W_NONLINEAR, gamma=1.4, adv_a=1.0,
              adv_b=0.0, cfl=0.9, eps=1e-6, lin_w=(0.994, 0.003, 0.003), gate_threshold=0.5,
              gate_every=1, positivity=False):
-        """positivity: the 1D Euler safeguard (not in the paper; off = the
-        paper's scheme)."""
+        """positivity: the Euler safeguard, 1D and 2D (not in the paper; off =
+        the paper's scheme)."""
         return cls(eq, int(charwise), weights, gamma, adv_a, adv_b, cfl, eps,
                    (ctypes.c_double * 3)(*lin_w), gate_threshold, gate_every, int(positivity))
 

@@ -24,6 +24,9 @@ struct Inst1D {
 struct Inst2D {
     long long off;
     long long cell_off;
+    long long face_off;        // positivity safeguard: first double of this instance's
+                               // face records (x-faces [20][ny][nx+1], then y-faces
+                               // [20][ny+1][nx])
     int nx, ny;
     int bc[4];
     double dx, dy;
@@ -83,6 +86,10 @@ struct Step2D {
                                // mode written by the gate kernel at each step)
     const GateLane *gate;      // packed network (LEARNED mode)
     float gate_logit_min;      // cells with logit >= this take the full reconstruction
+    double *faces;             // positivity safeguard (NULL: off): each face's averaged
+                               // flux and its values at t_{n+1} at the four edge nodes
+    uint8_t *trouble;          // safeguard: one byte per cell
+    int *guard;                // safeguard: per instance, repaired in this step
 };
 
 int sweep2d_tiles(int n_sweep, int n_trans, int lines);

@@ -71,7 +71,7 @@ struct Layout {
     size_t alt = 0, inst = 0, order = 0, queue = 0, ist = 0, t_end = 0, dt = 0,
            flags = 0, tiles0 = 0, tiles1 = 0, parity = 0, last = 0, dt_fixed = 0,
            steps_left = 0, smax = 0, bad = 0, active = 0, gate = 0, faces = 0, trouble = 0,
-           total = 0;
+           guard = 0, total = 0;
 };
 
 Layout make_layout(const shw_mesh *meshes, int n_inst, const shw_params *p)
@@ -102,10 +102,18 @@ Layout make_layout(const shw_mesh *meshes, int n_inst, const shw_params *p)
     L.bad = take((size_t)n_inst * sizeof(int));
     L.active = take(256);
     L.gate = take(64 * sizeof(GateLane));
-    // positivity safeguard (1D Euler): each face's flux and value at t_{n+1},
-    // planes [6][n+1] per instance, and a byte per cell
-    L.faces = take(p->positivity ? (cells + (size_t)n_inst) * 6 * sizeof(double) : 0);
+    // positivity safeguard (Euler): each face's flux and value(s) at t_{n+1}
+    // (1D: planes [6][n+1] per instance; 2D: [20][ny][nx+1] for the x-faces and
+    // [20][ny+1][nx] for the y-faces), a byte per cell, an int per instance
+    size_t face_doubles = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        const shw_mesh &m = meshes[i];
+        face_doubles += m.dim == 1 ? 6 * ((size_t)m.nx + 1)
+                                   : 20 * ((size_t)m.ny * (m.nx + 1) + (size_t)(m.ny + 1) * m.nx);
+    }
+    L.faces = take(p->positivity ? face_doubles * sizeof(double) : 0);
     L.trouble = take(p->positivity ? cells : 0);
+    L.guard = take(p->positivity ? (size_t)n_inst * sizeof(int) : 0);
     L.total = off;
     return L;
 }
@@ -173,7 +181,7 @@ static bool valid_batch(const shw_mesh *meshes, int n_inst, const shw_params *pa
         if (!valid_mesh(&meshes[i]) || meshes[i].dim != meshes[0].dim) return false;
     if (params->eq == SHW_BURGERS && meshes[0].dim != 1) return false;
     if (params->weights == SHW_W_LEARNED && params->eq != SHW_EULER) return false;
-    if (params->positivity && (params->eq != SHW_EULER || meshes[0].dim != 1)) return false;
+    if (params->positivity && params->eq != SHW_EULER) return false;
     return true;
 }
 
@@ -213,7 +221,7 @@ shw_status shw_create(const shw_mesh *meshes, int n_inst, const shw_params *para
     dp.charwise = params->charwise;
     dp.weights = params->weights;
 
-    long long o = 0, co = 0;
+    long long o = 0, co = 0, fo = 0;
     std::vector<Inst1D> i1;
     std::vector<Inst2D> i2;
     std::vector<int> toff[N_TILE_VARIANTS][2];
@@ -235,6 +243,8 @@ shw_status shw_create(const shw_mesh *meshes, int n_inst, const shw_params *para
             Inst2D d{};
             d.off = o;
             d.cell_off = co;
+            d.face_off = fo;
+            fo += 20LL * ((long long)m.ny * (m.nx + 1) + (long long)(m.ny + 1) * m.nx);
             d.nx = m.nx;
             d.ny = m.ny;
             for (int k = 0; k < 4; ++k) d.bc[k] = m.bc[k];
@@ -445,6 +455,11 @@ static Step2D step2d_args(shw_ctx *c)
     S.gate = c->at<GateLane>(c->lay.gate);
     const double th = c->params.gate_threshold;
     S.gate_logit_min = (th > 0.0 && th < 1.0) ? (float)std::log(th / (1.0 - th)) : 0.0f;
+    if (c->params.positivity) {
+        S.faces = c->at<double>(c->lay.faces);
+        S.trouble = c->at<uint8_t>(c->lay.trouble);
+        S.guard = c->at<int>(c->lay.guard);
+    }
     return S;
 }
 

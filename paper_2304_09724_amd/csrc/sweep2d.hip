@@ -114,6 +114,23 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks)
     return x * q + min(x, r) + b / XCDS;
 }
 
+// Positivity safeguard records (Euler): record q of a face, q < 4 the flux
+// averaged over the step and the edge, 4 + 4g + c component c of the value at
+// t_{n+1} at edge node g; components in the (x, y) frame.  An instance's
+// x-faces (row j, face f = 0..nx between cells f-1 and f) come first, then its
+// y-faces (column i, face f = 0..ny).
+constexpr int REC = 20;
+
+__device__ __forceinline__ long long xface_rec(const Inst2D &d, int q, int j, int f)
+{
+    return d.face_off + ((long long)q * d.ny + j) * (d.nx + 1) + f;
+}
+
+__device__ __forceinline__ long long yface_rec(const Inst2D &d, int q, int i, int f)
+{
+    return d.face_off + (long long)REC * d.ny * (d.nx + 1) + ((long long)q * (d.ny + 1) + f) * d.nx + i;
+}
+
 template <int EQ, int DIR, int L>
 __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
 {
@@ -292,6 +309,22 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
             Wu[g][c] = s_we[g][c][threadIdx.x + 1];
         }
     }
+    if constexpr (EQ == EULER) {
+        // the safeguard's record of this lane's lower face (each face once:
+        // lanes 2..61, and the last face of the line from lane 62)
+        if (S.faces && face && (lane <= 61 || s == ns)) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                const int cc = (DIR == 1 && (c == 1 || c == 2)) ? 3 - c : c;
+                const long long r0 = DIR == 0 ? xface_rec(d, cc, t, s) : yface_rec(d, cc, t, s);
+                const long long stride = DIR == 0 ? (long long)d.ny * (d.nx + 1)
+                                                  : (long long)(d.ny + 1) * d.nx;
+                S.faces[r0] = Fh[c];
+#pragma unroll
+                for (int g = 0; g < 4; ++g) S.faces[r0 + (long long)(M + M * g) * stride] = We[g][c];
+            }
+        }
+    }
     if (!(lane >= 2 && lane <= 61 && s >= 0 && s < ns)) return;
     const int i = DIR == 0 ? s : t, j = DIR == 0 ? t : s;
     const long long plane = (long long)d.nx * d.ny;
@@ -404,14 +437,20 @@ __global__ void clear_smax2d_kernel(Step2D S)
     if (i < S.n_inst) S.smax[i] = 0.0;
 }
 
+// which: 0 the caller's buffer, 1 the current state (by parity), 2 the output
+// of the step in flight (the other buffer); only: if set, the instances whose
+// entry is non-zero
 template <int EQ>
-__global__ void __launch_bounds__(BLOCK) speed2d_kernel(Step2D S, DevParams P, int use_parity)
+__global__ void __launch_bounds__(BLOCK) speed2d_kernel(Step2D S, DevParams P, int which,
+                                                        const int *only)
 {
     constexpr int M = NComp<EQ, 2>::M;
     __shared__ double red[LINES];
     const int inst = blockIdx.y;
+    if (only && !only[inst]) return;
     const Inst2D d = S.inst[inst];
-    const double *src = ((use_parity && S.parity[inst]) ? S.alt : S.state) + d.off;
+    const bool alt = which == 1 ? S.parity[inst] != 0 : which == 2 ? S.parity[inst] == 0 : false;
+    const double *src = (alt ? S.alt : S.state) + d.off;
     const long long plane = (long long)d.nx * d.ny;
     double m = 0.0;
     bool bad = false;
@@ -447,6 +486,151 @@ __global__ void __launch_bounds__(BLOCK) speed2d_kernel(Step2D S, DevParams P, i
         atomicMax(reinterpret_cast<unsigned long long *>(&S.smax[inst]),
                   (unsigned long long)__double_as_longlong(r));
         if (any_bad) atomicOr(&S.bad[inst], 1);
+    }
+}
+
+// ---- positivity safeguard (an addition to the paper's scheme; Euler) -----
+// After the sweeps of a step that left a non-physical average: cells whose
+// new average is non-physical are troubled (the test written as p = (g-1)(E -
+// (mx^2 + my^2)/(2 rho)) > 0, so the decision rounds as a plain evaluation of
+// that formula does); every x- and y-face next to a troubled cell takes the
+// first-order HLLE flux of the two averages at t_n, its state at x/t = 0
+// standing for the face value at all four edge nodes, and the cells on both
+// sides are updated again from the sweeps' records of their other faces
+// (conservative).  One round: a cell still non-physical stops its instance.
+__device__ __forceinline__ bool troubled2d(const double W[4], const DevParams &P)
+{
+    if (!isfinite(W[0]) || !isfinite(W[1]) || !isfinite(W[2]) || !isfinite(W[3]) ||
+        !(W[0] > 0.0))
+        return true;
+    double ke = 0.5 * W[1] * W[1] / W[0];
+    ke += 0.5 * W[2] * W[2] / W[0];
+    return !((P.gamma - 1.0) * (W[3] - ke) > 0.0);
+}
+
+__device__ __forceinline__ bool repairing(const Step2D &S, int inst)
+{
+    return S.bad[inst] != 0 && S.dt[inst] > 0.0;
+}
+
+__global__ void __launch_bounds__(BLOCK) guard_mark2d_kernel(Step2D S, DevParams P)
+{
+    const int inst = blockIdx.y;
+    if (!repairing(S, inst)) return;
+    const Inst2D d = S.inst[inst];
+    const double *out = (S.parity[inst] ? S.state : S.alt) + d.off;
+    const long long plane = (long long)d.nx * d.ny;
+    for (long long o = (long long)blockIdx.x * BLOCK + threadIdx.x; o < plane;
+         o += (long long)SPEED_SPLIT * BLOCK) {
+        const double W[4] = {out[o], out[plane + o], out[2 * plane + o], out[3 * plane + o]};
+        S.trouble[d.cell_off + o] = (uint8_t)troubled2d(W, P);
+    }
+}
+
+// HLLE face between two cells loaded from the state at t_n (ghosts by the
+// boundary conditions); dir 1: a y-face, solved with x and y exchanged
+__device__ void hlle2d(const Inst2D &d, const double *src, int i0, int j0, int i1, int j1,
+                       int dir, const DevParams &P, double F[4], double Ws[4])
+{
+    double WL[4], WR[4], V[4], Y[4], Z[4];
+    load_cell2d<EULER, 4, 0>(src, d, i0, j0, WL, V, Y, Z);
+    load_cell2d<EULER, 4, 0>(src, d, i1, j1, WR, V, Y, Z);
+    if (dir == 0) {
+        hlle_face<2>(WL, WR, P, F, Ws);
+        return;
+    }
+    const double RL[4] = {WL[0], WL[2], WL[1], WL[3]}, RR[4] = {WR[0], WR[2], WR[1], WR[3]};
+    double Fr[4], Sr[4];
+    hlle_face<2>(RL, RR, P, Fr, Sr);
+    F[0] = Fr[0]; F[1] = Fr[2]; F[2] = Fr[1]; F[3] = Fr[3];
+    Ws[0] = Sr[0]; Ws[1] = Sr[2]; Ws[2] = Sr[1]; Ws[3] = Sr[3];
+}
+
+__global__ void __launch_bounds__(BLOCK) guard_fix2d_kernel(Step2D S, DevParams P)
+{
+    constexpr int M = 4;
+    const int inst = blockIdx.y;
+    if (!repairing(S, inst)) return;
+    const Inst2D d = S.inst[inst];
+    const double *src = (S.parity[inst] ? S.alt : S.state) + d.off;
+    double *out = (S.parity[inst] ? S.state : S.alt) + d.off;
+    const uint8_t *tr = S.trouble + d.cell_off;
+    const long long plane = (long long)d.nx * d.ny;
+    const double dt = S.dt[inst];
+    const double nw[4] = {LOB_W0, LOB_W1, LOB_W1, LOB_W0};
+    const long long sx = (long long)d.ny * (d.nx + 1), sy = (long long)(d.ny + 1) * d.nx;
+    for (long long o = (long long)blockIdx.x * BLOCK + threadIdx.x; o < plane;
+         o += (long long)SPEED_SPLIT * BLOCK) {
+        const int i = (int)(o % d.nx), j = (int)(o / d.nx);
+        int k;
+        const int il = map_index(i - 1, d.nx, d.bc[0], d.bc[1], k);
+        const int ir = map_index(i + 1, d.nx, d.bc[0], d.bc[1], k);
+        const int jb = map_index(j - 1, d.ny, d.bc[2], d.bc[3], k);
+        const int jt = map_index(j + 1, d.ny, d.bc[2], d.bc[3], k);
+        const bool tc = tr[o] != 0;
+        const bool xl = tc || tr[(long long)j * d.nx + il] != 0;
+        const bool xr = tc || tr[(long long)j * d.nx + ir] != 0;
+        const bool yb = tc || tr[(long long)jb * d.nx + i] != 0;
+        const bool yt = tc || tr[(long long)jt * d.nx + i] != 0;
+        if (!(xl || xr || yb || yt)) continue;
+        // faces: flux and values at t_{n+1} at the four edge nodes
+        double F[4][M], E[4][4][M];          // [left, right, bottom, top]
+        const bool repl[4] = {xl, xr, yb, yt};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (repl[e]) {
+                double Fe[M], Ws[M];
+                if (e == 0) hlle2d(d, src, i - 1, j, i, j, 0, P, Fe, Ws);
+                else if (e == 1) hlle2d(d, src, i, j, i + 1, j, 0, P, Fe, Ws);
+                else if (e == 2) hlle2d(d, src, i, j - 1, i, j, 1, P, Fe, Ws);
+                else hlle2d(d, src, i, j, i, j + 1, 1, P, Fe, Ws);
+#pragma unroll
+                for (int c = 0; c < M; ++c) {
+                    F[e][c] = Fe[c];
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) E[e][g][c] = Ws[c];
+                }
+            } else {
+                const long long r0 = e == 0 ? xface_rec(d, 0, j, i) : e == 1 ? xface_rec(d, 0, j, i + 1)
+                                   : e == 2 ? yface_rec(d, 0, i, j) : yface_rec(d, 0, i, j + 1);
+                const long long st = e < 2 ? sx : sy;
+#pragma unroll
+                for (int c = 0; c < M; ++c) {
+                    F[e][c] = S.faces[r0 + c * st];
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) E[e][g][c] = S.faces[r0 + (M + M * g + c) * st];
+                }
+            }
+        }
+        const double rx = dt / d.dx, ry = dt / d.dy, iSS = 1.0 / (d.dx * d.dy);
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            double V = 0.0, Y = 0.0;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                V += nw[g] * (E[1][g][c] - E[0][g][c]);
+                Y += nw[g] * (E[3][g][c] - E[2][g][c]);
+            }
+            const double zx = E[1][3][c] - E[0][3][c] - E[1][0][c] + E[0][0][c];
+            const double zy = E[3][3][c] - E[2][3][c] - E[3][0][c] + E[2][0][c];
+            out[c * plane + o] = src[c * plane + o] - rx * (F[1][c] - F[0][c]) - ry * (F[3][c] - F[2][c]);
+            out[(M + c) * plane + o] = V / d.dx;
+            out[(2 * M + c) * plane + o] = Y / d.dy;
+            out[(3 * M + c) * plane + o] = 0.5 * (zx + zy) * iSS;
+        }
+    }
+}
+
+// per instance: a repaired instance gets its flag and CFL speed anew
+__global__ void guard_reset2d_kernel(Step2D S)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S.n_inst) return;
+    const int g = repairing(S, i) ? 1 : 0;
+    S.guard[i] = g;
+    if (g) {
+        S.bad[i] = 0;
+        S.smax[i] = 0.0;
     }
 }
 
@@ -522,8 +706,8 @@ hipError_t launch_speed2d(int eq, const Step2D &S, const DevParams &P, int use_p
 {
     clear_smax2d_kernel<<<(S.n_inst + 255) / 256, 256, 0, st>>>(S);
     const dim3 grid(SPEED_SPLIT, S.n_inst);
-    if (eq == EULER) speed2d_kernel<EULER><<<grid, BLOCK, 0, st>>>(S, P, use_parity);
-    else speed2d_kernel<ADV><<<grid, BLOCK, 0, st>>>(S, P, use_parity);
+    if (eq == EULER) speed2d_kernel<EULER><<<grid, BLOCK, 0, st>>>(S, P, use_parity, nullptr);
+    else speed2d_kernel<ADV><<<grid, BLOCK, 0, st>>>(S, P, use_parity, nullptr);
     return hipGetLastError();
 }
 
@@ -550,6 +734,15 @@ hipError_t launch_step2d(int eq, const Step2D &S, const DevParams &P, int fixed,
     if (lines == 1) sweeps2d<1>(eq, S, P, total_tiles, st);
     else if (lines == 2) sweeps2d<2>(eq, S, P, total_tiles, st);
     else sweeps2d<4>(eq, S, P, total_tiles, st);
+    if (eq == EULER && S.faces) {
+        // the positivity safeguard: every kernel returns at once for the
+        // instances whose step left no non-physical average
+        const dim3 grid(SPEED_SPLIT, S.n_inst);
+        guard_mark2d_kernel<<<grid, BLOCK, 0, st>>>(S, P);
+        guard_fix2d_kernel<<<grid, BLOCK, 0, st>>>(S, P);
+        guard_reset2d_kernel<<<nb, 256, 0, st>>>(S);
+        speed2d_kernel<EULER><<<grid, BLOCK, 0, st>>>(S, P, 2, S.guard);
+    }
     finish2d_kernel<<<nb, 256, 0, st>>>(S);
     return hipGetLastError();
 }

@@ -76,13 +76,15 @@ def test_learned_gate_is_euler_only():
         assert workspace(mesh, p) == 0
 
 
-def test_positivity_safeguard_is_1d_euler_only():
+def test_positivity_safeguard_is_euler_only():
     rect = S.Mesh.rect(16, 16, 0.0, 1.0, 0.0, 1.0)
     on = S.Params.make(eq=S.EULER, positivity=True)
     off = S.Params.make(eq=S.EULER)
     assert workspace(line(), on) > workspace(line(), off) > 0
-    assert workspace(rect, on) == 0
+    # 2D: 20 doubles for each of the 2 * 16 * 17 faces and a byte per cell
+    assert workspace(rect, on) >= workspace(rect, off) + 20 * 8 * 2 * 16 * 17 + 256
     assert workspace(line(), S.Params.make(eq=S.BURGERS, positivity=True)) == 0
+    assert workspace(rect, S.Params.make(eq=S.ADVECTION, positivity=True)) == 0
     bad = S.Params.make(eq=S.EULER)
     bad.positivity = 2
     assert state_doubles(line(), bad) == 0

@@ -164,6 +164,70 @@ def test_isentropic_vortex_paper_table():
     assert np.all(orders > 4.5), orders
 
 
+def test_positivity_safeguard_2d_against_oracle():
+    """The safeguard in 2D (not in the paper): the four-quadrant data of the
+    batch's instance 75, which fail at step 4 under the paper's scheme, run 12
+    steps on a periodic 16^2 grid and 8 steps on a transmissive 64^2 grid; the
+    GPU matches the oracle's runs with the same safeguard step for step."""
+    quads = WL.four_quadrant_batch(count=256)[75].quads
+    for n, bc, steps in ((16, S.BC_PERIODIC, 12), (64, S.BC_TRANSMISSIVE, 8)):
+        st = WL.four_quadrant(n, quads)
+        s = S.Solver([S.Mesh.rect(n, n, 0.0, 1.0, 0.0, 1.0, bc, bc)],
+                     S.Params.make(eq=S.EULER, positivity=True))
+        s.set_state(0, st)
+        k = s.advance_to(1.0, max_steps=steps)
+        assert k[0] == steps and s.instance_status()[0] == 0
+        obc = O.BC_PERIODIC if bc == S.BC_PERIODIC else O.BC_TRANSMISSIVE
+        cfg = O.Config(eq=O.EULER, bc=(obc,) * 4, positivity=True)
+        o, t, osteps, bad = O.advance2d(cfg, st, 1.0 / n, 1.0 / n, 0.9, 1.0, max_steps=steps)
+        assert not bad and osteps == steps
+        assert rel_err(s.get_state(0), o) < TOL, n
+
+
+def test_positivity_safeguard_2d_unchanged_where_not_needed():
+    """A ragged batch of smooth states runs bit for bit the same with the
+    safeguard on and off."""
+    sizes = [(12, 20), (70, 9), (33, 33)]
+    runs = []
+    for pos in (False, True):
+        s = S.Solver([S.Mesh.rect(nx, ny, 0.0, 1.0, 0.0, 1.0) for nx, ny in sizes],
+                     S.Params.make(eq=S.EULER, positivity=pos))
+        for i, (nx, ny) in enumerate(sizes):
+            s.set_state(i, smooth_state(nx, ny, seed=i))
+        s.advance_to(np.full(len(sizes), 1.0), max_steps=5)
+        runs.append([s.get_state(i) for i in range(len(sizes))])
+    for a, b in zip(*runs):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_positivity_safeguard_2d_batch_failures():
+    """Four-quadrant problems of the batch (n <= 384), run to t = 0.25: three of
+    the first 64 meet a non-physical state under the paper's scheme; with the
+    safeguard two of them complete.  The third (instance 120, 384^2) still
+    stops at step 3: next to the quadrants' corner a cell's update with the
+    first-order HLLE flux on all four faces is itself non-physical at CFL 0.9
+    (sum form), and the oracle with the same safeguard stops at the same step."""
+    insts = WL.four_quadrant_batch(count=256)
+    pick = [i for i, d in enumerate(insts) if d.n <= 384][:64]
+    sub = [insts[i] for i in pick]
+    meshes = [S.Mesh.rect(d.n, d.n, 0.0, 1.0, 0.0, 1.0, S.BC_TRANSMISSIVE, S.BC_TRANSMISSIVE)
+              for d in sub]
+    failed, steps = [], []
+    for pos in (False, True):
+        s = S.Solver(meshes, S.Params.make(eq=S.EULER, positivity=pos))
+        for k, d in enumerate(sub):
+            s.set_state(k, d.state())
+        steps.append(s.advance_to(np.full(len(sub), 0.25), raise_nonphysical=False))
+        failed.append({pick[k] for k in np.nonzero(s.instance_status())[0]})
+    print(f"failures without the safeguard {sorted(failed[0])}, with it {sorted(failed[1])}")
+    assert failed[0] == {75, 120, 126}
+    assert failed[1] == {120}
+    d = insts[120]
+    cfg = O.Config(eq=O.EULER, bc=(O.BC_TRANSMISSIVE,) * 4, positivity=True)
+    o, t, osteps, bad = O.advance2d(cfg, d.state(), 1.0 / d.n, 1.0 / d.n, 0.9, 0.25, max_steps=3)
+    assert bad and osteps == 3 and steps[1][pick.index(120)] == 3
+
+
 def test_advection_2d():
     n = 16
     st = smooth_state(n, n, 9)[:, :1].copy()          # one component
