@@ -194,6 +194,10 @@ SHW_HD void face1d(const Re JL[5][M], const Re JR[5][M], double dt, const DevPar
         char_1d(Ws, P.gamma, E);
         const Re lam[M] = {E.u - E.c, E.u, E.u + E.c};
         const Re scale = fabs(E.u) + E.c;
+        // each field's side, chosen once for the four derivative orders
+        Re wl[M], wr[M];
+#pragma unroll
+        for (int s = 0; s < M; ++s) upwind_weights(lam[s], scale, wl[s], wr[s]);
 #pragma unroll
         for (int c = 0; c < M; ++c) w[c][0][0] = Ws[c];
         const double inv_fact[5] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
@@ -203,7 +207,7 @@ SHW_HD void face1d(const Re JL[5][M], const Re JR[5][M], double dt, const DevPar
             char1_L(E, JL[a], l);
             char1_L(E, JR[a], r);
 #pragma unroll
-            for (int s = 0; s < M; ++s) ch[s] = upwind(lam[s], scale, l[s], r[s]);
+            for (int s = 0; s < M; ++s) ch[s] = upwind_blend(wl[s], wr[s], l[s], r[s]);
             char1_R(E, ch, d);
 #pragma unroll
             for (int c = 0; c < M; ++c) w[c][a][0] = d[c] * inv_fact[a];

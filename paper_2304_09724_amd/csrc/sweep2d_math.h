@@ -256,6 +256,7 @@ template <int M, int EQ, class Re>
 struct Leading2D {
     Re Ws[M], scale;
     CharX<Re> E;     // Euler: characteristic fields at Ws (speeds u-c, u, u, u+c)
+    Re wl[M], wr[M]; // Euler: each field's upwind weights, shared by the 14 seeds
     Re lam0;         // advection: the speed
 };
 
@@ -267,6 +268,9 @@ SHW_HD void grp2d_leading(const Re JL[M], const Re JR[M], const DevParams &P, do
         hllc_state<2>(JL, JR, P.gamma, G.Ws);
         char_x(G.Ws, P.gamma, G.E);
         G.scale = fabs(G.E.u) + G.E.c;
+        const Re lam[M] = {G.E.u - G.E.c, G.E.u, G.E.u, G.E.u + G.E.c};
+#pragma unroll
+        for (int f = 0; f < M; ++f) upwind_weights(lam[f], G.scale, G.wl[f], G.wr[f]);
     } else {
         G.lam0 = as;
         G.scale = fabs(as);
@@ -282,9 +286,8 @@ SHW_HD void grp2d_seed(const Re JL[M], const Re JR[M], const Leading2D<M, EQ, Re
         Re l[M], r[M], ch[M];
         char_L(G.E, JL, l);
         char_L(G.E, JR, r);
-        const Re lam[M] = {G.E.u - G.E.c, G.E.u, G.E.u, G.E.u + G.E.c};
 #pragma unroll
-        for (int f = 0; f < M; ++f) ch[f] = upwind(lam[f], G.scale, l[f], r[f]);
+        for (int f = 0; f < M; ++f) ch[f] = upwind_blend(G.wl[f], G.wr[f], l[f], r[f]);
         char_R(G.E, ch, out);
 #pragma unroll
         for (int c = 0; c < M; ++c) out[c] *= factor;
