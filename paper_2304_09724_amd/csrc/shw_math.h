@@ -7,6 +7,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 // Every arithmetic routine is a template on the real type R: the kernels use
 // R = double; a host build with an operation-counting type measures the
@@ -30,6 +31,83 @@ struct DevParams {
     int charwise;
     int weights;
 };
+
+// ---------------------------------------------------------------------------
+// Reciprocals, quotients and square roots of the state arithmetic.  On the
+// device in double precision they start from the hardware's approximate
+// reciprocal (v_rcp_f64) or reciprocal square root (v_rsq_f64) and take two
+// steps of Newton's iteration r <- r + r (1 - x r), or of Goldschmidt's
+// iteration for sqrt(x) and 1/sqrt(x) together (g = x y, h = y/2;
+// r = 1/2 - g h; g <- g + g r, h <- h + h r), each step squaring the relative
+// error.  The results lie within about an ulp of the correctly rounded ones
+// over the normal range (IEEE division and sqrt round to half an ulp but take
+// twice the instructions).  A zero, negative, infinite or NaN argument gives
+// a NaN or an infinity, as IEEE arithmetic gives a non-finite or a
+// non-physical value there, so the step's checks still catch the state.
+// Every other build (the host, the operation-counting type) uses IEEE
+// division and sqrt, and counts one division or root per call.
+// ---------------------------------------------------------------------------
+template <class R>
+SHW_HD R recip(R x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (std::is_same<R, double>::value) {
+        double r = __builtin_amdgcn_rcp(x);
+        double e = fma(-x, r, 1.0);
+        r = fma(r, e, r);
+        e = fma(-x, r, 1.0);
+        return fma(r, e, r);
+    }
+#endif
+    return 1.0 / x;
+}
+
+// a / b as a times the reciprocal of b (two roundings after the refinement).
+template <class R>
+SHW_HD R quot(R a, R b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (std::is_same<R, double>::value) return a * recip(b);
+#endif
+    return a / b;
+}
+
+// s = sqrt(x) and is = 1/sqrt(x).
+template <class R>
+SHW_HD void sqrt_rsqrt(R x, R &s, R &is)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (std::is_same<R, double>::value) {
+        const double y = __builtin_amdgcn_rsq(x);
+        double g = x * y, h = 0.5 * y;
+        double r = fma(-g, h, 0.5);
+        g = fma(g, r, g);
+        h = fma(h, r, h);
+        r = fma(-g, h, 0.5);
+        g = fma(g, r, g);
+        h = fma(h, r, h);
+        s = g;
+        is = h + h;
+        return;
+    }
+#endif
+    s = sqrt(x);
+    is = 1.0 / s;
+}
+
+// sqrt(x) alone, from the same iteration (the reciprocal is not counted).
+template <class R>
+SHW_HD R sqrt_fast(R x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (std::is_same<R, double>::value) {
+        double s, is;
+        sqrt_rsqrt(x, s, is);
+        return s;
+    }
+#endif
+    return sqrt(x);
+}
 
 template <int EQ, int DIM>
 struct NComp { static constexpr int M = (EQ == EULER) ? (DIM == 1 ? 3 : 4) : 1; };
@@ -83,7 +161,7 @@ SHW_HD void nonlinear_weights(const R c[5], R am, R a0, R ap, const DevParams &P
     const R w1 = P.g1 * (d1 + tau) * (d2 * d3);
     const R w2 = P.g2 * (d2 + tau) * (d1 * d3);
     const R w3 = P.g3 * (d3 + tau) * (d1 * d2);
-    const R inv = 1.0 / (w1 + w2 + w3);
+    const R inv = recip(w1 + w2 + w3);
     w[0] = w1 * inv;
     w[1] = w2 * inv;
     w[2] = w3 * inv;
@@ -191,12 +269,11 @@ struct Char1 {
 template <class Re>
 SHW_HD void char_1d(const Re *W, double gamma, Char1<Re> &E)
 {
-    const Re ir = 1.0 / W[0];
+    const Re ir = recip(W[0]);
     E.u = W[1] * ir;
     E.hq = 0.5 * E.u * E.u;
     const Re p = (gamma - 1.0) * (W[2] - W[0] * E.hq);
-    E.c = sqrt(gamma * p * ir);
-    E.ic = 1.0 / E.c;
+    sqrt_rsqrt(gamma * p * ir, E.c, E.ic);
     E.H = (W[2] + p) * ir;
     E.b1 = (gamma - 1.0) * (E.ic * E.ic);
     E.b2 = E.b1 * E.hq;
@@ -236,13 +313,12 @@ struct CharX {
 template <class Re>
 SHW_HD void char_x(const Re *W, double gamma, CharX<Re> &E)
 {
-    const Re ir = 1.0 / W[0];
+    const Re ir = recip(W[0]);
     E.u = W[1] * ir;
     E.v = W[2] * ir;
     E.hq = 0.5 * (E.u * E.u + E.v * E.v);
     const Re p = (gamma - 1.0) * (W[3] - W[0] * E.hq);
-    E.c = sqrt(gamma * p * ir);
-    E.ic = 1.0 / E.c;
+    sqrt_rsqrt(gamma * p * ir, E.c, E.ic);
     E.H = (W[3] + p) * ir;
     E.b1 = (gamma - 1.0) * (E.ic * E.ic);
     E.b2 = E.b1 * E.hq;
@@ -306,7 +382,7 @@ SHW_HD void hllc_state(const R *WL, const R *WR, double gamma, R *Ws)
 {
     constexpr int M = NComp<EULER, DIM>::M;
     const R rl = WL[0], rr = WR[0];
-    const R irl = 1.0 / rl, irr = 1.0 / rr;
+    const R irl = recip(rl), irr = recip(rr);
     const R ul = WL[1] * irl, ur = WR[1] * irr;
     R kl = WL[1] * ul, kr = WR[1] * ur;                   // rho |u|^2
     if constexpr (DIM == 2) {
@@ -315,11 +391,11 @@ SHW_HD void hllc_state(const R *WL, const R *WR, double gamma, R *Ws)
     }
     const R pl = (gamma - 1.0) * (WL[M - 1] - 0.5 * kl);
     const R pr = (gamma - 1.0) * (WR[M - 1] - 0.5 * kr);
-    const R cl = sqrt(gamma * pl * irl), cr = sqrt(gamma * pr * irr);
+    const R cl = sqrt_fast(gamma * pl * irl), cr = sqrt_fast(gamma * pr * irr);
     const R SL = fmin(ul - cl, ur - cr);
     const R SR = fmax(ul + cl, ur + cr);
     const R ml = rl * (SL - ul), mr = rr * (SR - ur);
-    const R Ss = (pr - pl + ul * ml - ur * mr) / (ml - mr);
+    const R Ss = quot(pr - pl + ul * ml - ur * mr, ml - mr);
     if (0.0 <= SL) {
 #pragma unroll
         for (int c = 0; c < M; ++c) Ws[c] = WL[c];
@@ -335,11 +411,11 @@ SHW_HD void hllc_state(const R *WL, const R *WR, double gamma, R *Ws)
     const R uk = left ? ul : ur, pk = left ? pl : pr;
     const R SK = left ? SL : SR, mk = left ? ml : mr;
     const R irk = left ? irl : irr;
-    const R f = mk / (SK - Ss);
+    const R f = quot(mk, SK - Ss);
     Ws[0] = f;
     Ws[1] = f * Ss;
     if constexpr (DIM == 2) Ws[2] = f * (WK[2] * irk);
-    Ws[M - 1] = f * (WK[M - 1] * irk + (Ss - uk) * (Ss + pk / mk));
+    Ws[M - 1] = f * (WK[M - 1] * irk + (Ss - uk) * (Ss + quot(pk, mk)));
 }
 
 // First-order HLLE flux F and state Ws at x/t = 0 in the normal direction x

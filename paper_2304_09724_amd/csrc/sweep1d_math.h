@@ -139,7 +139,7 @@ SHW_HD void ck1d(R w[M][5][5], const DevParams &P)
     } else {
         const double gm1 = P.gamma - 1.0;
         // velocity by series division (rho u = m), no reciprocal series
-        const R r00 = 1.0 / w[0][0][0];
+        const R r00 = recip(w[0][0][0]);
         R u[5][5], mu[5][5], p[5][5], ep[5][5], epu[5][5];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -257,10 +257,10 @@ SHW_HD R wave_speed(const R *W, const DevParams &P)
     if constexpr (EQ == ADV) return R(fabs(P.adv_a));
     else if constexpr (EQ == BURG) return fabs(W[0]);
     else {
-        const R ir = 1.0 / W[0];
+        const R ir = recip(W[0]);
         const R u = W[1] * ir;
         const R p = (P.gamma - 1.0) * (W[2] - 0.5 * W[1] * u);
-        return fabs(u) + sqrt(P.gamma * p * ir);
+        return fabs(u) + sqrt_fast(P.gamma * p * ir);
     }
 }
 
