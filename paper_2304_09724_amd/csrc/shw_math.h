@@ -358,13 +358,13 @@ SHW_HD void phys_flux_x(const R *W, const DevParams &P, R *F)
     } else if constexpr (EQ == BURG) {
         F[0] = 0.5 * W[0] * W[0];
     } else if constexpr (DIM == 1) {
-        const R u = W[1] / W[0];
+        const R u = quot(W[1], W[0]);
         const R p = (P.gamma - 1.0) * (W[2] - 0.5 * W[1] * u);
         F[0] = W[1];
         F[1] = W[1] * u + p;
         F[2] = (W[2] + p) * u;
     } else {
-        const R ir = 1.0 / W[0];
+        const R ir = recip(W[0]);
         const R u = W[1] * ir;
         const R p = (P.gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) * ir);
         F[0] = W[1];
