@@ -82,9 +82,16 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
         // lanes past the end read the last ghost cell and discard the result
         const int jl = live ? j : n;
         double Wm[M], Vm[M], W0[M], V0[M], Wp[M], Vp[M];
-        load_cell<EQ, M>(src, n, jl - 1, d.bc_lo, d.bc_hi, Wm, Vm);
-        const int s0 = load_cell<EQ, M>(src, n, jl, d.bc_lo, d.bc_hi, W0, V0);
-        load_cell<EQ, M>(src, n, jl + 1, d.bc_lo, d.bc_hi, Wp, Vp);
+        int s0 = jl;
+        if (ch * CHUNK - 2 >= 0 && ch * CHUNK + CHUNK + 1 <= n - 1) {
+            // the whole chunk's stencil (cells 62 ch - 2 .. 62 ch + 63) is
+            // inside the instance: the same for every lane of the wave
+            load_inner<M>(src, n, jl, Wm, Vm, W0, V0, Wp, Vp);
+        } else {
+            load_cell<EQ, M>(src, n, jl - 1, d.bc_lo, d.bc_hi, Wm, Vm);
+            s0 = load_cell<EQ, M>(src, n, jl, d.bc_lo, d.bc_hi, W0, V0);
+            load_cell<EQ, M>(src, n, jl + 1, d.bc_lo, d.bc_hi, Wp, Vp);
+        }
         bool full = P.weights == W_NONLINEAR;
         if (P.weights == W_GATED) full = flags[d.cell_off + s0] != 0;
         if constexpr (LRN) {

@@ -40,6 +40,21 @@ __device__ __forceinline__ int load_cell(const double *__restrict__ base, int n,
 }
 
 
+// data of cells j-1, j, j+1 when all three lie inside the instance (no
+// boundary condition in force)
+template <int M>
+__device__ __forceinline__ void load_inner(const double *__restrict__ base, int n, int j,
+                                           double Wm[M], double Vm[M], double W0[M],
+                                           double V0[M], double Wp[M], double Vp[M])
+{
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        const double *w = base + (long long)c * n + j, *v = base + (long long)(M + c) * n + j;
+        Wm[c] = w[-1]; W0[c] = w[0]; Wp[c] = w[1];
+        Vm[c] = v[-1]; V0[c] = v[0]; Vp[c] = v[1];
+    }
+}
+
 // Step 1: reconstruction of one cell; lo/hi receive d^a W/dx^a at the left
 // and right edge, a = 0..4.  full: nonlinear weights, else the linear ones
 // (the big quartic alone).  charpath (Euler, characteristic reconstruction
