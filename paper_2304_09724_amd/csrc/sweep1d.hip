@@ -172,16 +172,21 @@ __device__ void gate_pass(const Inst1D &d, const double *__restrict__ src, const
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int n = d.n;
     const int nchunk = (n + CHUNK - 1) / CHUNK;
+    const GateLane G = gate_lane_lds(gate, lane);
     for (int ch = wave; ch < nchunk; ch += NB / WAVE) {
         const int j = ch * CHUNK + lane - 1;
         const int jl = j <= n ? j : n;
         double Wm[M], Vm[M], W0[M], V0[M], Wp[M], Vp[M];
-        load_cell<EULER, M>(src, n, jl - 1, d.bc_lo, d.bc_hi, Wm, Vm);
-        load_cell<EULER, M>(src, n, jl, d.bc_lo, d.bc_hi, W0, V0);
-        load_cell<EULER, M>(src, n, jl + 1, d.bc_lo, d.bc_hi, Wp, Vp);
+        if (ch * CHUNK - 2 >= 0 && ch * CHUNK + CHUNK + 1 <= n - 1) {
+            load_inner<M>(src, n, jl, Wm, Vm, W0, V0, Wp, Vp);
+        } else {
+            load_cell<EULER, M>(src, n, jl - 1, d.bc_lo, d.bc_hi, Wm, Vm);
+            load_cell<EULER, M>(src, n, jl, d.bc_lo, d.bc_hi, W0, V0);
+            load_cell<EULER, M>(src, n, jl + 1, d.bc_lo, d.bc_hi, Wp, Vp);
+        }
         float f[GATE_NF];
         gate_features1d(Wm, W0, Wp, Vm, Vp, d.dx, P.gamma, f);
-        const bool full = gate_wave_logit(f, gate_lane_lds(gate, lane)) >= gate_logit_min;
+        const bool full = gate_wave_logit(f, G) >= gate_logit_min;
         if (lane >= 1 && lane <= CHUNK && j >= 0 && j < n) flags[d.cell_off + j] = (uint8_t)full;
     }
 }
