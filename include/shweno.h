@@ -54,8 +54,8 @@ enum { SHW_ADVECTION = 0, SHW_BURGERS = 1, SHW_EULER = 2 };
 enum { SHW_BC_PERIODIC = 0, SHW_BC_TRANSMISSIVE = 1, SHW_BC_REFLECTIVE = 2 };
 enum { SHW_W_NONLINEAR = 0, SHW_W_LINEAR = 1, SHW_W_GATED = 2, SHW_W_LEARNED = 3 };
 
-/* Number of parameters of the learned gate's network (8-32-32-1):
- * W1[32][8], b1[32], W2[32][32], b2[32], w3[32], b3, in that order. */
+/* Number of parameters of the learned gate's network (16-32-32-1):
+ * W1[32][16], b1[32], W2[32][32], b2[32], w3[32], b3, in that order. */
 #define SHW_GATE_NFEATURES 16
 #define SHW_GATE_NPARAMS 1633
 

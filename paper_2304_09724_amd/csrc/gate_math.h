@@ -1,5 +1,5 @@
 // gate_math.h -- the learned troubled-cell gate on the device: cell features,
-// training labels, and the 8-32-32-1 network evaluated by one wave with
+// training labels, and the 16-32-32-1 network evaluated by one wave with
 // BF16 matrix-core instructions (FP32 accumulation).
 //
 // The gate is an addition to the paper's method: a cell it passes as smooth
