@@ -79,29 +79,36 @@ SHW_HD void recon_cell(const Re Wm[M], const Re W0[M], const Re Wp[M], const Re 
             char1_L(E, Wp, cp);
             char1_L(E, Vm, dm);
             char1_L(E, Vp, dp);
-            Re clo[M][5], chi[M][5];
+            Re cq[M][5];
 #pragma unroll
             for (int s = 0; s < M; ++s) {
-                Re q[5];
-                big_quartic(cm[s], c0[s], cp[s], Re(dx * dm[s]), Re(dx * dp[s]), q);
+                big_quartic(cm[s], c0[s], cp[s], Re(dx * dm[s]), Re(dx * dp[s]), cq[s]);
                 if (full) {
                     Re w[3];
-                    nonlinear_weights(q, cm[s], c0[s], cp[s], P, w);
-                    combine(q, cm[s], c0[s], cp[s], w, P);
+                    nonlinear_weights(cq[s], cm[s], c0[s], cp[s], P, w);
+                    combine(cq[s], cm[s], c0[s], cp[s], w, P);
                 }
-                edge_derivs(q, clo[s], chi[s]);
+            }
+            // back to the components on the five coefficients (R is linear:
+            // the same polynomial as mapping the ten edge jets), then the
+            // edge derivatives of each component
+            Re pq[M][5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const Re y[M] = {cq[0][k], cq[1][k], cq[2][k]};
+                Re x[M];
+                char1_R(E, y, x);
+#pragma unroll
+                for (int c = 0; c < M; ++c) pq[c][k] = x[c];
             }
 #pragma unroll
-            for (int a = 0; a < 5; ++a) {
-                const Re yl[M] = {clo[0][a], clo[1][a], clo[2][a]};
-                const Re yh[M] = {chi[0][a], chi[1][a], chi[2][a]};
-                Re l[M], h[M];
-                char1_R(E, yl, l);
-                char1_R(E, yh, h);
+            for (int c = 0; c < M; ++c) {
+                Re l5[5], h5[5];
+                edge_derivs(pq[c], l5, h5);
 #pragma unroll
-                for (int c = 0; c < M; ++c) {
-                    lo[a][c] = l[c] * sc[a];
-                    hi[a][c] = h[c] * sc[a];
+                for (int a = 0; a < 5; ++a) {
+                    lo[a][c] = l5[a] * sc[a];
+                    hi[a][c] = h5[a] * sc[a];
                 }
             }
             return;
@@ -251,9 +258,13 @@ SHW_HD void face1d(const Re JL[5][M], const Re JR[5][M], double dt, const DevPar
     for (int q = 0; q < 4; ++q) {
         const double tau = taus[q];
         Re Wt[M], F[M];
+        // at tau = 0 the series is its constant term (the same value: the
+        // compiler may not drop the zero products itself, since 0 * x is not
+        // zero for every x)
 #pragma unroll
         for (int c = 0; c < M; ++c)
-            Wt[c] = w[c][0][0] + tau * (w[c][0][1] + tau * (w[c][0][2] + tau * (w[c][0][3] + tau * w[c][0][4])));
+            Wt[c] = q == 0 ? w[c][0][0]
+                           : w[c][0][0] + tau * (w[c][0][1] + tau * (w[c][0][2] + tau * (w[c][0][3] + tau * w[c][0][4])));
         phys_flux_x<EQ, 1>(Wt, P, F);
 #pragma unroll
         for (int c = 0; c < M; ++c) Fh[c] += wts[q] * F[c];

@@ -336,9 +336,12 @@ SHW_HD void node_flux(const Re wt[M][5], double dt, const DevParams &P, double a
     for (int q = 0; q < 4; ++q) {
         const double tau = taus[q];
         Re Wt[M], Fq[M];
+        // at tau = 0 the series is its constant term (0 * x is not zero for
+        // every x, so the compiler keeps the products otherwise)
 #pragma unroll
         for (int c = 0; c < M; ++c)
-            Wt[c] = wt[c][0] + tau * (wt[c][1] + tau * (wt[c][2] + tau * (wt[c][3] + tau * wt[c][4])));
+            Wt[c] = q == 0 ? wt[c][0]
+                           : wt[c][0] + tau * (wt[c][1] + tau * (wt[c][2] + tau * (wt[c][3] + tau * wt[c][4])));
         if constexpr (EQ == EULER) {
             phys_flux_x<EULER, 2>(Wt, P, Fq);
         } else {
