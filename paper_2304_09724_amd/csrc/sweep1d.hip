@@ -74,6 +74,8 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
     const int n = d.n;
     const int nchunk = (n + CHUNK - 1) / CHUNK;
     const double idx = 1.0 / d.dx, dt_dx = dt * idx;
+    double js[5];
+    jet_scales(idx, js);
     bool bad = false;
     double spd = 0.0;       // largest wave speed of the new averages of this lane
     for (int ch = wave; ch < nchunk; ch += NB / WAVE) {
@@ -111,7 +113,7 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
         // one reconstruction path per wave: characteristic if any lane needs
         // the nonlinear weights
         const bool charpath = __any(full);
-        recon_cell<EQ, M>(Wm, W0, Wp, Vm, Vp, d.dx, idx, full, charpath, P, lo, hi);
+        recon_cell<EQ, M>(Wm, W0, Wp, Vm, Vp, d.dx, full, charpath, P, lo, hi);
         // right-edge jet of the left neighbour
         double prev[5][M];
 #pragma unroll
@@ -120,7 +122,7 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
             for (int c = 0; c < M; ++c) prev[a][c] = from_lane_below(hi[a][c]);
         double Fh[M], We[M];
         if (lane >= 1 && j >= 0 && live) {
-            face1d<EQ, M>(prev, lo, dt, P, Fh, We);
+            face1d<EQ, M>(prev, lo, js, dt, P, Fh, We);
         } else {
 #pragma unroll
             for (int c = 0; c < M; ++c) { Fh[c] = 0.0; We[c] = 0.0; }

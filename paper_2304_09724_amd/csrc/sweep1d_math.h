@@ -55,8 +55,10 @@ __device__ __forceinline__ void load_inner(const double *__restrict__ base, int 
     }
 }
 
-// Step 1: reconstruction of one cell; lo/hi receive d^a W/dx^a at the left
-// and right edge, a = 0..4.  full: nonlinear weights, else the linear ones
+// Step 1: reconstruction of one cell; lo/hi receive d^a W/dxi^a at the left
+// and right edge, a = 0..4, in the cell's coordinate xi = (x - x_j)/dx (the
+// face turns them into x-derivatives: the derivative Riemann problems are
+// linear in the jets, so one per-instance factor per order serves both).  full: nonlinear weights, else the linear ones
 // (the big quartic alone).  charpath (Euler, characteristic reconstruction
 // on): work in characteristic fields; a cell with linear weights gets the
 // same polynomial either way (the big quartic is linear in its data), up to
@@ -64,11 +66,9 @@ __device__ __forceinline__ void load_inner(const double *__restrict__ base, int 
 // component-wise form serves waves without nonlinear cells.
 template <int EQ, int M, class Re>
 SHW_HD void recon_cell(const Re Wm[M], const Re W0[M], const Re Wp[M], const Re Vm[M],
-                       const Re Vp[M], double dx, double idx, bool full, bool charpath,
+                       const Re Vp[M], double dx, bool full, bool charpath,
                        const DevParams &P, Re lo[5][M], Re hi[5][M])
 {
-    double sc[5];
-    sc[0] = 1.0; sc[1] = idx; sc[2] = idx * idx; sc[3] = sc[2] * idx; sc[4] = sc[2] * sc[2];
     if constexpr (EQ == EULER) {
         if (charpath && P.charwise) {
             Char1<Re> E;
@@ -107,8 +107,8 @@ SHW_HD void recon_cell(const Re Wm[M], const Re W0[M], const Re Wp[M], const Re 
                 edge_derivs(pq[c], l5, h5);
 #pragma unroll
                 for (int a = 0; a < 5; ++a) {
-                    lo[a][c] = l5[a] * sc[a];
-                    hi[a][c] = h5[a] * sc[a];
+                    lo[a][c] = l5[a];
+                    hi[a][c] = h5[a];
                 }
             }
             return;
@@ -126,8 +126,8 @@ SHW_HD void recon_cell(const Re Wm[M], const Re W0[M], const Re Wp[M], const Re 
         edge_derivs(q, l5, h5);
 #pragma unroll
         for (int a = 0; a < 5; ++a) {
-            lo[a][c] = l5[a] * sc[a];
-            hi[a][c] = h5[a] * sc[a];
+            lo[a][c] = l5[a];
+            hi[a][c] = h5[a];
         }
     }
 }
@@ -200,12 +200,24 @@ SHW_HD void ck1d(R w[M][5][5], const DevParams &P)
     }
 }
 
-// Steps 2-4 at one face: GRP from the two one-sided jets, then the flux of
-// eq. (flux) with the 4-point Gauss-Lobatto rule in time and the interface
-// state at t + dt (eq. (tay1d)).
+// Per-instance factors of face1d: js[a] = dx^-a / a!, turning the jets' xi-
+// derivatives of order a into Taylor coefficients in x.
+SHW_HD void jet_scales(double idx, double js[5])
+{
+    js[0] = 1.0;
+    js[1] = idx;
+    js[2] = 0.5 * idx * idx;
+    js[3] = (1.0 / 6.0) * idx * idx * idx;
+    js[4] = (1.0 / 24.0) * (idx * idx) * (idx * idx);
+}
+
+// Steps 2-4 at one face: GRP from the two one-sided jets (xi-derivatives of
+// the cells on either side; js from jet_scales), then the flux of eq. (flux)
+// with the 4-point Gauss-Lobatto rule in time and the interface state at
+// t + dt (eq. (tay1d)).
 template <int EQ, int M, class Re>
-SHW_HD void face1d(const Re JL[5][M], const Re JR[5][M], double dt, const DevParams &P,
-                   Re Fh[M], Re We[M])
+SHW_HD void face1d(const Re JL[5][M], const Re JR[5][M], const double js[5], double dt,
+                   const DevParams &P, Re Fh[M], Re We[M])
 {
     Re w[M][5][5];
     // leading term (sec. 2.1.1) and the derivative Riemann problems (eq. (lineq))
@@ -222,7 +234,6 @@ SHW_HD void face1d(const Re JL[5][M], const Re JR[5][M], double dt, const DevPar
         for (int s = 0; s < M; ++s) upwind_weights(lam[s], scale, wl[s], wr[s]);
 #pragma unroll
         for (int c = 0; c < M; ++c) w[c][0][0] = Ws[c];
-        const double inv_fact[5] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
 #pragma unroll
         for (int a = 1; a < 5; ++a) {
             Re l[M], r[M], ch[M], d[M];
@@ -232,7 +243,7 @@ SHW_HD void face1d(const Re JL[5][M], const Re JR[5][M], double dt, const DevPar
             for (int s = 0; s < M; ++s) ch[s] = upwind_blend(wl[s], wr[s], l[s], r[s]);
             char1_R(E, ch, d);
 #pragma unroll
-            for (int c = 0; c < M; ++c) w[c][a][0] = d[c] * inv_fact[a];
+            for (int c = 0; c < M; ++c) w[c][a][0] = d[c] * js[a];
         }
     } else {
         Re lam;
@@ -243,10 +254,9 @@ SHW_HD void face1d(const Re JL[5][M], const Re JR[5][M], double dt, const DevPar
             w[0][0][0] = burgers_state(JL[0][0], JR[0][0]);
             lam = w[0][0][0];
         }
-        const double inv_fact[5] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
 #pragma unroll
         for (int a = 1; a < 5; ++a)
-            w[0][a][0] = upwind(lam, fabs(lam), JL[a][0], JR[a][0]) * inv_fact[a];
+            w[0][a][0] = upwind(lam, fabs(lam), JL[a][0], JR[a][0]) * js[a];
     }
     ck1d<EQ, M>(w, P);
     // Gauss-Lobatto in time over [t_n, t_n + dt]

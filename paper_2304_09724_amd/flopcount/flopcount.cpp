@@ -86,9 +86,11 @@ static void euler1d(bool full, const char *name)
     Cnt s = wave_speed<EULER>(W0, P);
     (void)s;
     Cnt lo[5][M], hi[5][M];
-    recon_cell<EULER, M>(Wm, W0, Wp, Vm, Vp, 0.01, 100.0, full, full, P, lo, hi);
+    recon_cell<EULER, M>(Wm, W0, Wp, Vm, Vp, 0.01, full, full, P, lo, hi);
     Cnt Fh[M], We[M];
-    face1d<EULER, M>(hi, lo, 0.004, P, Fh, We);
+    double js[5];
+    jet_scales(100.0, js);
+    face1d<EULER, M>(hi, lo, js, 0.004, P, Fh, We);
     Cnt Wn[M], Vn[M];
     update1d<M>(W0, Fh, Fh, We, We, 0.4, 100.0, Wn, Vn);
     report(name, g, "cell-update");
