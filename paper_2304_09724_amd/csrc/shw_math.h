@@ -471,21 +471,14 @@ SHW_HD R upwind(R lam, R scale, R l, R r)
 }
 
 // The same choice as weights of the two sides, (1, 0), (0, 1) or (1/2, 1/2),
-// for a speed shared by several problems: w_l l + w_r r gives upwind()'s
-// value bit for bit (halving is exact, so 0.5 l + 0.5 r rounds as 0.5 (l + r)).
+// for a speed shared by several problems (they sum to one, so a problem can
+// be solved on the jump: x_r + w_l (x_l - x_r)).
 template <class R>
 SHW_HD void upwind_weights(R lam, R scale, R &wl, R &wr)
 {
     const R z = 1e-10 * scale;
     wl = lam > z ? R(1.0) : (lam < -z ? R(0.0) : R(0.5));
     wr = lam > z ? R(0.0) : (lam < -z ? R(1.0) : R(0.5));
-}
-
-// Applies upwind_weights: the side (or mean) they pick.
-template <class R>
-SHW_HD R upwind_blend(R wl, R wr, R l, R r)
-{
-    return wl * l + wr * r;
 }
 
 // Exact Godunov state of Burgers' equation at x/t = 0 (sec. 2.1.1, scalar case).

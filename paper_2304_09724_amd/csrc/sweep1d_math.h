@@ -236,14 +236,18 @@ SHW_HD void face1d(const Re JL[5][M], const Re JR[5][M], const double js[5], dou
         for (int c = 0; c < M; ++c) w[c][0][0] = Ws[c];
 #pragma unroll
         for (int a = 1; a < 5; ++a) {
-            Re l[M], r[M], ch[M], d[M];
-            char1_L(E, JL[a], l);
-            char1_L(E, JR[a], r);
+            // solved on the jump: each field's weights sum to one, so
+            // R (w_l L x_L + w_r L x_R) = x_R + R (w_l L (x_L - x_R)) as R L = I,
+            // one projection instead of two
+            Re dj[M], l[M], d[M];
 #pragma unroll
-            for (int s = 0; s < M; ++s) ch[s] = upwind_blend(wl[s], wr[s], l[s], r[s]);
-            char1_R(E, ch, d);
+            for (int c = 0; c < M; ++c) dj[c] = JL[a][c] - JR[a][c];
+            char1_L(E, dj, l);
 #pragma unroll
-            for (int c = 0; c < M; ++c) w[c][a][0] = d[c] * js[a];
+            for (int s = 0; s < M; ++s) l[s] = wl[s] * l[s];
+            char1_R(E, l, d);
+#pragma unroll
+            for (int c = 0; c < M; ++c) w[c][a][0] = (JR[a][c] + d[c]) * js[a];
         }
     } else {
         Re lam;

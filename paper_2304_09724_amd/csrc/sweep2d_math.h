@@ -256,7 +256,8 @@ template <int M, int EQ, class Re>
 struct Leading2D {
     Re Ws[M], scale;
     CharX<Re> E;     // Euler: characteristic fields at Ws (speeds u-c, u, u, u+c)
-    Re wl[M], wr[M]; // Euler: each field's upwind weights, shared by the 14 seeds
+    Re wl[M];        // Euler: each field's upwind weight of the left side (the
+                     // right one is 1 - wl), shared by the 14 seeds
     Re lam0;         // advection: the speed
 };
 
@@ -270,7 +271,10 @@ SHW_HD void grp2d_leading(const Re JL[M], const Re JR[M], const DevParams &P, do
         G.scale = fabs(G.E.u) + G.E.c;
         const Re lam[M] = {G.E.u - G.E.c, G.E.u, G.E.u, G.E.u + G.E.c};
 #pragma unroll
-        for (int f = 0; f < M; ++f) upwind_weights(lam[f], G.scale, G.wl[f], G.wr[f]);
+        for (int f = 0; f < M; ++f) {
+            Re wr;
+            upwind_weights(lam[f], G.scale, G.wl[f], wr);
+        }
     } else {
         G.lam0 = as;
         G.scale = fabs(as);
@@ -283,14 +287,18 @@ SHW_HD void grp2d_seed(const Re JL[M], const Re JR[M], const Leading2D<M, EQ, Re
                        double factor, Re out[M])
 {
     if constexpr (EQ == EULER) {
-        Re l[M], r[M], ch[M];
-        char_L(G.E, JL, l);
-        char_L(G.E, JR, r);
+        // solved on the jump: each field's weights sum to one, so
+        // R (w_l L x_L + w_r L x_R) = x_R + R (w_l L (x_L - x_R)) as R L = I,
+        // one projection instead of two
+        Re dj[M], l[M], d[M];
 #pragma unroll
-        for (int f = 0; f < M; ++f) ch[f] = upwind_blend(G.wl[f], G.wr[f], l[f], r[f]);
-        char_R(G.E, ch, out);
+        for (int c = 0; c < M; ++c) dj[c] = JL[c] - JR[c];
+        char_L(G.E, dj, l);
 #pragma unroll
-        for (int c = 0; c < M; ++c) out[c] *= factor;
+        for (int f = 0; f < M; ++f) l[f] = G.wl[f] * l[f];
+        char_R(G.E, l, d);
+#pragma unroll
+        for (int c = 0; c < M; ++c) out[c] = (JR[c] + d[c]) * factor;
     } else {
         out[0] = upwind(G.lam0, G.scale, JL[0], JR[0]) * factor;
     }

@@ -5,9 +5,7 @@
 // and runs it once on representative data.  Every +, -, *, / and sqrt the
 // kernel source performs on state-dependent values is counted once; a fused
 // multiply-add counts as two.  Work on per-instance constants (dx, dt and the
-// like) is not counted, and applying an upwind choice through weights counts
-// as the choice itself (a mean at zero speed as one add and one multiply).
-// Prints one JSON object per path.
+// like) is not counted.  Prints one JSON object per path.
 #include <cmath>
 #include <cstdio>
 
@@ -48,14 +46,6 @@ static inline Cnt sqrt(Cnt a) { ++g.sqrt; return std::sqrt(a.v); }
 static inline Cnt fabs(Cnt a) { return std::fabs(a.v); }
 static inline Cnt fmin(Cnt a, Cnt b) { return std::fmin(a.v, b.v); }
 static inline Cnt fmax(Cnt a, Cnt b) { return std::fmax(a.v, b.v); }
-
-// found by argument-dependent lookup ahead of the template in shw_math.h
-static inline Cnt upwind_blend(Cnt wl, Cnt wr, Cnt l, Cnt r)
-{
-    if (wr.v == 0.0) return l;
-    if (wl.v == 0.0) return r;
-    return 0.5 * (l + r);
-}
 
 #include "../csrc/sweep1d_math.h"
 #include "../csrc/sweep2d_math.h"
