@@ -72,9 +72,9 @@ SHW_HD R quot(R a, R b)
     return a / b;
 }
 
-// s = sqrt(x) and is = 1/sqrt(x).
+// s = sqrt(x) and hs = 1/(2 sqrt(x)) (the iteration's own h).
 template <class R>
-SHW_HD void sqrt_rsqrt(R x, R &s, R &is)
+SHW_HD void sqrt_hrsqrt(R x, R &s, R &hs)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
     if constexpr (std::is_same<R, double>::value) {
@@ -87,13 +87,14 @@ SHW_HD void sqrt_rsqrt(R x, R &s, R &is)
         g = fma(g, r, g);
         h = fma(h, r, h);
         s = g;
-        is = h + h;
+        hs = h;
         return;
     }
 #endif
     s = sqrt(x);
-    is = 1.0 / s;
+    hs = 0.5 / s;
 }
+
 
 // sqrt(x) alone, from the same iteration (the reciprocal is not counted).
 template <class R>
@@ -101,8 +102,8 @@ SHW_HD R sqrt_fast(R x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
     if constexpr (std::is_same<R, double>::value) {
-        double s, is;
-        sqrt_rsqrt(x, s, is);
+        double s, hs;
+        sqrt_hrsqrt(x, s, hs);
         return s;
     }
 #endif
@@ -260,10 +261,13 @@ SHW_HD void euler_eigen(const Re *W, double gamma, Re R[][NComp<EULER, DIM>::M],
 // The characteristic fields of the 1D Euler flux Jacobian at a state, held
 // as the seven numbers its eigenvectors are built from instead of the 18
 // entries of R and L (the matrices of euler_eigen<1, 0>): speeds u - c, u,
-// u + c.  char1_L and char1_R apply L and R in closed form.
+// u + c.  char1_L and char1_R apply L and R in closed form.  With b1 =
+// (g-1)/c^2 and b2 = b1 u^2/2, L's coefficients are kept halved (hb1 = b1/2,
+// hb2 = b2/2, hic = 1/(2c)): two of L's rows carry a factor 1/2, which then
+// costs nothing, and halving is exact, so the rows' values are unchanged.
 template <class Re>
 struct Char1 {
-    Re u, c, ic, H, b1, b2, hq;      // hq = u^2 / 2
+    Re u, c, hic, H, hb1, hb2, hq;   // hq = u^2 / 2
 };
 
 template <class Re>
@@ -273,22 +277,23 @@ SHW_HD void char_1d(const Re *W, double gamma, Char1<Re> &E)
     E.u = W[1] * ir;
     E.hq = 0.5 * E.u * E.u;
     const Re p = (gamma - 1.0) * (W[2] - W[0] * E.hq);
-    sqrt_rsqrt(gamma * p * ir, E.c, E.ic);
+    sqrt_hrsqrt(gamma * p * ir, E.c, E.hic);
     E.H = (W[2] + p) * ir;
-    E.b1 = (gamma - 1.0) * (E.ic * E.ic);
-    E.b2 = E.b1 * E.hq;
+    E.hb1 = (2.0 * (gamma - 1.0)) * (E.hic * E.hic);
+    E.hb2 = E.hb1 * E.hq;
 }
 
 // y = L x: rows (b2 + u/c, -(b1 u + 1/c), b1)/2, (1 - b2, b1 u, -b1),
-// (b2 - u/c, -(b1 u - 1/c), b1)/2
+// (b2 - u/c, -(b1 u - 1/c), b1)/2; with s = b2 x0 - b1 (u x1 - x2) and
+// d = (u x0 - x1)/c: y = ((s + d)/2, x0 - s, (s - d)/2), formed from s/2, d/2
 template <class Re>
 SHW_HD void char1_L(const Char1<Re> &E, const Re x[3], Re y[3])
 {
-    const Re s = E.b2 * x[0] - E.b1 * (E.u * x[1] - x[2]);
-    const Re d = E.ic * (E.u * x[0] - x[1]);
-    y[0] = 0.5 * (s + d);
-    y[1] = x[0] - s;
-    y[2] = 0.5 * (s - d);
+    const Re hs = E.hb2 * x[0] - E.hb1 * (E.u * x[1] - x[2]);
+    const Re hd = E.hic * (E.u * x[0] - x[1]);
+    y[0] = hs + hd;
+    y[1] = x[0] - 2.0 * hs;
+    y[2] = hs - hd;
 }
 
 // x = R y: columns (1, u - c, H - u c), (1, u, u^2/2), (1, u + c, H + u c)
@@ -307,7 +312,7 @@ SHW_HD void char1_R(const Char1<Re> &E, const Re y[3], Re x[3])
 // u - c, u, u, u + c.  char_L and char_R apply L and R in closed form.
 template <class Re>
 struct CharX {
-    Re u, v, c, ic, H, b1, b2, hq;   // hq = |u|^2 / 2
+    Re u, v, c, hic, H, hb1, hb2, hq;   // hq = |u|^2 / 2; halved as in Char1
 };
 
 template <class Re>
@@ -318,23 +323,24 @@ SHW_HD void char_x(const Re *W, double gamma, CharX<Re> &E)
     E.v = W[2] * ir;
     E.hq = 0.5 * (E.u * E.u + E.v * E.v);
     const Re p = (gamma - 1.0) * (W[3] - W[0] * E.hq);
-    sqrt_rsqrt(gamma * p * ir, E.c, E.ic);
+    sqrt_hrsqrt(gamma * p * ir, E.c, E.hic);
     E.H = (W[3] + p) * ir;
-    E.b1 = (gamma - 1.0) * (E.ic * E.ic);
-    E.b2 = E.b1 * E.hq;
+    E.hb1 = (2.0 * (gamma - 1.0)) * (E.hic * E.hic);
+    E.hb2 = E.hb1 * E.hq;
 }
 
 // y = L x: rows (b2 + u/c, -(b1 u + 1/c), -b1 v, b1)/2, (1 - b2, b1 u, b1 v,
-// -b1), (-v, 0, 1, 0), (b2 - u/c, -(b1 u - 1/c), -b1 v, b1)/2
+// -b1), (-v, 0, 1, 0), (b2 - u/c, -(b1 u - 1/c), -b1 v, b1)/2; formed from the
+// halves of s = b2 x0 - b1 (u x1 + v x2 - x3) and d = (u x0 - x1)/c as in char1_L
 template <class Re>
 SHW_HD void char_L(const CharX<Re> &E, const Re x[4], Re y[4])
 {
-    const Re s = E.b2 * x[0] - E.b1 * (E.u * x[1] + E.v * x[2] - x[3]);
-    const Re d = E.ic * (E.u * x[0] - x[1]);
-    y[0] = 0.5 * (s + d);
-    y[1] = x[0] - s;
+    const Re hs = E.hb2 * x[0] - E.hb1 * (E.u * x[1] + E.v * x[2] - x[3]);
+    const Re hd = E.hic * (E.u * x[0] - x[1]);
+    y[0] = hs + hd;
+    y[1] = x[0] - 2.0 * hs;
     y[2] = x[2] - E.v * x[0];
-    y[3] = 0.5 * (s - d);
+    y[3] = hs - hd;
 }
 
 // x = R y: columns (1, u - c, v, H - u c), (1, u, v, |u|^2/2), (0, 0, 1, v),

@@ -73,20 +73,29 @@ SHW_HD void recon_cell(const Re Wm[M], const Re W0[M], const Re Wp[M], const Re 
         if (charpath && P.charwise) {
             Char1<Re> E;
             char_1d(W0, P.gamma, E);
-            Re cm[M], c0[M], cp[M], dm[M], dp[M];
-            char1_L(E, Wm, cm);
-            char1_L(E, W0, c0);
-            char1_L(E, Wp, cp);
+            // Adding a constant to the three averages adds it to the big
+            // quartic's and the combined polynomial's constant term and
+            // changes no smoothness indicator or weight; so the fields are
+            // reconstructed from the neighbours' differences to this cell's
+            // average (its own field values then being zero), and the
+            // average is added back to the components' constant term below.
+            Re em[M], ep[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) { em[c] = Wm[c] - W0[c]; ep[c] = Wp[c] - W0[c]; }
+            Re cm[M], cp[M], dm[M], dp[M];
+            char1_L(E, em, cm);
+            char1_L(E, ep, cp);
             char1_L(E, Vm, dm);
             char1_L(E, Vp, dp);
+            const Re zero = 0.0;
             Re cq[M][5];
 #pragma unroll
             for (int s = 0; s < M; ++s) {
-                big_quartic(cm[s], c0[s], cp[s], Re(dx * dm[s]), Re(dx * dp[s]), cq[s]);
+                big_quartic(cm[s], zero, cp[s], Re(dx * dm[s]), Re(dx * dp[s]), cq[s]);
                 if (full) {
                     Re w[3];
-                    nonlinear_weights(cq[s], cm[s], c0[s], cp[s], P, w);
-                    combine(cq[s], cm[s], c0[s], cp[s], w, P);
+                    nonlinear_weights(cq[s], cm[s], zero, cp[s], P, w);
+                    combine(cq[s], cm[s], zero, cp[s], w, P);
                 }
             }
             // back to the components on the five coefficients (R is linear:
@@ -101,6 +110,8 @@ SHW_HD void recon_cell(const Re Wm[M], const Re W0[M], const Re Wp[M], const Re 
 #pragma unroll
                 for (int c = 0; c < M; ++c) pq[c][k] = x[c];
             }
+#pragma unroll
+            for (int c = 0; c < M; ++c) pq[c][0] += W0[c];
 #pragma unroll
             for (int c = 0; c < M; ++c) {
                 Re l5[5], h5[5];
