@@ -145,14 +145,14 @@ SHW_HD void big_quartic(R am, R a0, R ap, R bm, R bp, R c[5])
 // sum_k int (d^k p/dxi^k)^2 over the cell; for the quartic that integral is
 // the quadratic form below (exact integration of the squared derivatives).
 // Simple-WENO weights: tau = ((|b1-b2| + |b1-b3|)/2)^2,
-// w_l ~ g_l (1 + tau/(b_l + eps)).
+// w_l ~ g_l (1 + tau/(b_l + eps)).  The _jumps form takes dl = a0 - am and
+// dr = ap - a0, all the averages enter through.
 template <class R>
-SHW_HD void nonlinear_weights(const R c[5], R am, R a0, R ap, const DevParams &P, R w[3])
+SHW_HD void nonlinear_weights_jumps(const R c[5], R dl, R dr, const DevParams &P, R w[3])
 {
     const R b1 = c[1] * c[1] + 0.5 * c[1] * c[3] + (13.0 / 3.0) * c[2] * c[2]
                     + (21.0 / 5.0) * c[2] * c[4] + (3129.0 / 80.0) * c[3] * c[3]
                     + (87617.0 / 140.0) * c[4] * c[4];
-    const R dl = a0 - am, dr = ap - a0;
     const R b2 = dl * dl, b3 = dr * dr;
     R tau = 0.5 * (fabs(b1 - b2) + fabs(b1 - b3));
     tau = tau * tau;
@@ -168,6 +168,12 @@ SHW_HD void nonlinear_weights(const R c[5], R am, R a0, R ap, const DevParams &P
     w[2] = w3 * inv;
 }
 
+template <class R>
+SHW_HD void nonlinear_weights(const R c[5], R am, R a0, R ap, const DevParams &P, R w[3])
+{
+    nonlinear_weights_jumps(c, a0 - am, ap - a0, P, w);
+}
+
 // Final polynomial (w1/g1)(p1 - g2 p2 - g3 p3) + w2 p2 + w3 p3 in place of the
 // quartic coefficients c (the linear candidates only touch xi^0 and xi^1).
 template <class R>
@@ -176,6 +182,19 @@ SHW_HD void combine(R c[5], R am, R a0, R ap, const R w[3], const DevParams &P)
     const R f = w[0] * P.inv_g1;
     const R dl = a0 - am, dr = ap - a0;
     c[0] = f * (c[0] - (P.g2 + P.g3) * a0) + (w[1] + w[2]) * a0;
+    c[1] = f * (c[1] - P.g2 * dl - P.g3 * dr) + w[1] * dl + w[2] * dr;
+    c[2] *= f;
+    c[3] *= f;
+    c[4] *= f;
+}
+
+// combine for centred data (a0 = 0, so the candidates' constant terms drop
+// out): the same coefficients as combine(c, -dl, 0, dr, ...).
+template <class R>
+SHW_HD void combine_centred(R c[5], R dl, R dr, const R w[3], const DevParams &P)
+{
+    const R f = w[0] * P.inv_g1;
+    c[0] = f * c[0];
     c[1] = f * (c[1] - P.g2 * dl - P.g3 * dr) + w[1] * dl + w[2] * dr;
     c[2] *= f;
     c[3] *= f;

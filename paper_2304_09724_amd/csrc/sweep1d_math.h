@@ -94,8 +94,8 @@ SHW_HD void recon_cell(const Re Wm[M], const Re W0[M], const Re Wp[M], const Re 
                 big_quartic(cm[s], zero, cp[s], Re(dx * dm[s]), Re(dx * dp[s]), cq[s]);
                 if (full) {
                     Re w[3];
-                    nonlinear_weights(cq[s], cm[s], zero, cp[s], P, w);
-                    combine(cq[s], cm[s], zero, cp[s], w, P);
+                    nonlinear_weights_jumps(cq[s], -cm[s], cp[s], P, w);
+                    combine_centred(cq[s], -cm[s], cp[s], w, P);
                 }
             }
             // back to the components on the five coefficients (R is linear:
