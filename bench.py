@@ -42,7 +42,8 @@ def log(msg):
 
 # HBM bytes of one launch of the persistent kernel on this workload, from the
 # two counter runs summarised in profiles/ (FETCH_SIZE and WRITE_SIZE scaled by
-# a 1 GiB copy); valid only for the kernel sources those runs measured.
+# a 1 GiB copy); valid only for the kernel code those runs measured (the
+# sources compared without their comments and with whitespace collapsed).
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "loop1d_euler_riemann4096_hbm_counters.md")
 KERNEL_SOURCES = ["sweep1d.hip", "shw_kernels.h", "sweep1d_math.h", "shw_math.h", "gate_math.h",
                   "lanes.h"]
@@ -50,10 +51,14 @@ KERNEL_SOURCES = ["sweep1d.hip", "shw_kernels.h", "sweep1d_math.h", "shw_math.h"
 
 def kernel_fingerprint():
     import hashlib
+    import re
+    # string literals kept, // and /* */ comments dropped, whitespace runs as one blank
+    token = re.compile(r'"(?:\\.|[^"\\])*"|//[^\n]*|/\*.*?\*/', re.S)
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2304_09724_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2304_09724_amd", "csrc", f)) as fh:
+            text = token.sub(lambda m: m.group(0) if m.group(0).startswith('"') else " ", fh.read())
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

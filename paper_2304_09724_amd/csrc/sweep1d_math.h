@@ -58,9 +58,10 @@ __device__ __forceinline__ void load_inner(const double *__restrict__ base, int 
 // Step 1: reconstruction of one cell; lo/hi receive d^a W/dxi^a at the left
 // and right edge, a = 0..4, in the cell's coordinate xi = (x - x_j)/dx (the
 // face turns them into x-derivatives: the derivative Riemann problems are
-// linear in the jets, so one per-instance factor per order serves both).  full: nonlinear weights, else the linear ones
-// (the big quartic alone).  charpath (Euler, characteristic reconstruction
-// on): work in characteristic fields; a cell with linear weights gets the
+// linear in the jets, so one per-instance factor per order serves both).
+// full: nonlinear weights, else the linear ones (the big quartic alone).
+// charpath (Euler, characteristic reconstruction on): work in
+// characteristic fields; a cell with linear weights gets the
 // same polynomial either way (the big quartic is linear in its data), up to
 // rounding, so callers choose the path once for a whole wave and the cheap
 // component-wise form serves waves without nonlinear cells.
@@ -240,9 +241,13 @@ SHW_HD void face1d(const Re JL[5][M], const Re JR[5][M], const double js[5], dou
         const Re lam[M] = {E.u - E.c, E.u, E.u + E.c};
         const Re scale = fabs(E.u) + E.c;
         // each field's side, chosen once for the four derivative orders
-        Re wl[M], wr[M];
+        // (the right side's weight is 1 - wl)
+        Re wl[M];
 #pragma unroll
-        for (int s = 0; s < M; ++s) upwind_weights(lam[s], scale, wl[s], wr[s]);
+        for (int s = 0; s < M; ++s) {
+            Re wr;
+            upwind_weights(lam[s], scale, wl[s], wr);
+        }
 #pragma unroll
         for (int c = 0; c < M; ++c) w[c][0][0] = Ws[c];
 #pragma unroll
