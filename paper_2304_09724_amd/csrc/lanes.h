@@ -4,7 +4,9 @@
 // The DPP wavefront shifts of the GFX9 family move a 32-bit value one lane up
 // ("wave_shr:1": lane l receives lane l - 1) or down ("wave_shl:1": lane l
 // receives lane l + 1) inside the register file.  The lane left without a
-// neighbour (lane 0 up, lane 63 down) receives 0; the sweeps never read it.
+// neighbour (lane 0 up, lane 63 down) receives 0 (bound_ctrl: the hardware
+// writes the zero, so no old value has to be set up first); the sweeps never
+// read it.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,8 +20,8 @@ template <int CTRL>
 __device__ __forceinline__ double lane_shift(double x)
 {
     const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
