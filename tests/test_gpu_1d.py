@@ -127,6 +127,23 @@ def test_lax_tube_full_run():
     assert rel_err(g, o) < TOL
 
 
+@pytest.mark.parametrize("scale", [1e-8, 1e8])
+def test_scaled_states_full_run(scale):
+    """Multiplying density, momentum and energy (so also pressure) by one
+    factor leaves velocities and sound speeds, and so the step sizes,
+    unchanged, while every reciprocal and square root of the state works at
+    another exponent.  Lax's tube scaled by 1e-8 and 1e8, against the oracle
+    on the same scaled data (the weights' epsilon makes the scheme itself
+    only nearly scale-free)."""
+    n = 200
+    st = WL.lax_tube(n) * scale
+    _, (g,), steps = run_gpu([S.Mesh.line(n, -5.0, 5.0, S.BC_TRANSMISSIVE)], gparams(S.EULER),
+                             [st], 1.3)
+    o, t, osteps, bad = O.advance1d(ocfg(O.EULER, O.BC_TRANSMISSIVE), st, 10.0 / n, 0.9, 1.3)
+    assert not bad and steps[0] == osteps
+    assert rel_err(g, o) < TOL
+
+
 def test_blast_waves_full_runs():
     """The interacting blast waves (sec. 5), reflective walls, T = 0.038, in
     one batch: at 400 cells the whole run (705 steps) against the oracle's; at
