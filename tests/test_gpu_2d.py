@@ -72,6 +72,26 @@ def test_single_step_tile_edges_and_boundaries(nx, ny, bc):
     assert rel_err(g, o) < TOL
 
 
+@pytest.mark.parametrize("scale", [1e-8, 1e8])
+def test_scaled_states_steps(scale):
+    """As in 1D: density, momenta and energy times one factor keep every
+    velocity and sound speed, while the sweeps' reciprocals and square roots
+    work at another exponent.  Five fixed steps on a 61 x 64 mesh (ragged in
+    both tile directions), against the oracle on the same scaled data."""
+    nx, ny = 61, 64
+    st = smooth_state(nx, ny, 17) * scale
+    dt = 0.2 / max(nx, ny)
+    s = S.Solver([S.Mesh.rect(nx, ny, 0.0, 1.0, 0.0, 1.0, S.BC_PERIODIC, S.BC_TRANSMISSIVE)],
+                 gparams())
+    s.set_state(0, st)
+    o = st
+    for _ in range(5):
+        s.step([dt])
+        o, bad = O.step2d(ocfg(O.BC_PERIODIC, O.BC_TRANSMISSIVE), o, 1.0 / nx, 1.0 / ny, dt)
+        assert not bad
+    assert rel_err(s.get_state(0), o) < TOL
+
+
 def test_mixed_boundaries():
     nx, ny = 23, 17
     st = smooth_state(nx, ny, 3)
