@@ -167,7 +167,7 @@ def gated_leg(S, insts, states, meshes, init, args, plain_value, plain):
     params, hist = GT.train(X, y)
     train_s = time.perf_counter() - t0
     threshold = 0.05
-    every = 2
+    every = 3
     g = S.Solver(meshes, S.Params.make(eq=S.EULER, cfl=0.9, weights=S.W_LEARNED,
                                        gate_threshold=threshold, gate_every=every),
                  device="cuda:0")
