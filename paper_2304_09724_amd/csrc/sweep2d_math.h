@@ -162,37 +162,40 @@ SHW_HD void stage2_order(int n, const Re am[M], const Re a0[M], const Re ap[M], 
             char_L(E, bp, dp);
         }
     }
-    Re clo[M][5], chi[M][5];
+    Re cq[M][5];
 #pragma unroll
     for (int f = 0; f < M; ++f) {
         const Re xm = cm[f], x0 = c0[f], xp = cp[f], ym = dm[f], yp = dp[f];
-        Re q[5];
-        big_quartic(xm, x0, xp, Re(dS * ym), Re(dS * yp), q);
+        big_quartic(xm, x0, xp, Re(dS * ym), Re(dS * yp), cq[f]);
         if (full) {
-            if (n == 0) nonlinear_weights(q, xm, x0, xp, P, w[f]);
-            combine(q, xm, x0, xp, w[f], P);
+            if (n == 0) nonlinear_weights(cq[f], xm, x0, xp, P, w[f]);
+            combine(cq[f], xm, x0, xp, w[f], P);
         }
-        edge_derivs(q, clo[f], chi[f]);
     }
+    if constexpr (EQ == EULER) {
+        if (proj) {
+            // back to the components on the five coefficients (R is linear:
+            // the same polynomials as mapping the 2 (5 - n) edge jets)
 #pragma unroll
-    for (int a = 0; a < 5; ++a) {
-        if (a + n > 4) continue;
-        Re l[M], h[M];
+            for (int k = 0; k < 5; ++k) {
+                Re y[M], x[M];
 #pragma unroll
-        for (int f = 0; f < M; ++f) { l[f] = clo[f][a]; h[f] = chi[f][a]; }
-        if constexpr (EQ == EULER) {
-            if (proj) {
-                Re tl[M], th[M];
-                char_R(E, l, tl);
-                char_R(E, h, th);
+                for (int f = 0; f < M; ++f) y[f] = cq[f][k];
+                char_R(E, y, x);
 #pragma unroll
-                for (int c = 0; c < M; ++c) { l[c] = tl[c]; h[c] = th[c]; }
+                for (int c = 0; c < M; ++c) cq[c][k] = x[c];
             }
         }
+    }
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-            lo[a][c] = l[c] * scs[a];
-            hi[a][c] = h[c] * scs[a];
+    for (int c = 0; c < M; ++c) {
+        Re l5[5], h5[5];
+        edge_derivs(cq[c], l5, h5);
+#pragma unroll
+        for (int a = 0; a < 5; ++a) {
+            if (a + n > 4) continue;
+            lo[a][c] = l5[a] * scs[a];
+            hi[a][c] = h5[a] * scs[a];
         }
     }
 }
