@@ -39,34 +39,36 @@ SHW_HD void stage1(const Re W[3][M], const Re V[3][M], const Re Y[3][M], const R
 {
     if constexpr (EQ == EULER) {
         if (charpath && P.charwise) {
-            Re R[M][M], L[M][M], lam[M];
-            euler_eigen<2, 1>(W[1], P.gamma, R, L, lam);
+            // The transverse Jacobian's fields (those of euler_eigen<2, 1>)
+            // in closed form: the x-direction fields of the state with its
+            // two momenta swapped, applied to data with the momenta swapped
+            // (un-swapping R's rows gives exactly euler_eigen<2, 1>'s columns,
+            // scaling included).
+            const Re Ws[M] = {W[1][0], W[1][2], W[1][1], W[1][3]};
+            CharX<Re> E;
+            char_x(Ws, P.gamma, E);
+            Re pw[3][M], pv[3][M], py[2][M], pz[2][M];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const Re xw[M] = {W[l][0], W[l][2], W[l][1], W[l][3]};
+                const Re xv[M] = {V[l][0], V[l][2], V[l][1], V[l][3]};
+                char_L(E, xw, pw[l]);
+                char_L(E, xv, pv[l]);
+            }
+#pragma unroll
+            for (int l = 0; l < 2; ++l) {
+                const Re xy[M] = {Y[2 * l][0], Y[2 * l][2], Y[2 * l][1], Y[2 * l][3]};
+                const Re xz[M] = {Z[2 * l][0], Z[2 * l][2], Z[2 * l][1], Z[2 * l][3]};
+                char_L(E, xy, py[l]);
+                char_L(E, xz, pz[l]);
+            }
             Re cw[M][5], cv[M][5];
 #pragma unroll
             for (int f = 0; f < M; ++f) {
-                Re aw[3], av[3], bw[2], bv[2];
-#pragma unroll
-                for (int l = 0; l < 3; ++l) {
-                    Re sw = 0.0, sv = 0.0;
-#pragma unroll
-                    for (int c = 0; c < M; ++c) {
-                        sw += L[f][c] * W[l][c];
-                        sv += L[f][c] * V[l][c];
-                    }
-                    aw[l] = sw;
-                    av[l] = sv;
-                }
-#pragma unroll
-                for (int l = 0; l < 2; ++l) {
-                    Re sy = 0.0, sz = 0.0;
-#pragma unroll
-                    for (int c = 0; c < M; ++c) {
-                        sy += L[f][c] * Y[2 * l][c];
-                        sz += L[f][c] * Z[2 * l][c];
-                    }
-                    bw[l] = dT * sy;
-                    bv[l] = dT * sz;
-                }
+                const Re aw[3] = {pw[0][f], pw[1][f], pw[2][f]};
+                const Re av[3] = {pv[0][f], pv[1][f], pv[2][f]};
+                const Re bw[2] = {dT * py[0][f], dT * py[1][f]};
+                const Re bv[2] = {dT * pz[0][f], dT * pz[1][f]};
                 big_quartic(aw[0], aw[1], aw[2], bw[0], bw[1], cw[f]);
                 big_quartic(av[0], av[1], av[2], bv[0], bv[1], cv[f]);
                 if (full) {
@@ -77,18 +79,16 @@ SHW_HD void stage1(const Re W[3][M], const Re V[3][M], const Re Y[3][M], const R
                 }
             }
 #pragma unroll
-            for (int c = 0; c < M; ++c)
-#pragma unroll
-                for (int k = 0; k < 5; ++k) {
-                    Re sw = 0.0, sv = 0.0;
-#pragma unroll
-                    for (int f = 0; f < M; ++f) {
-                        sw += R[c][f] * cw[f][k];
-                        sv += R[c][f] * cv[f][k];
-                    }
-                    PW[c][k] = sw;
-                    PV[c][k] = sv;
-                }
+            for (int k = 0; k < 5; ++k) {
+                const Re yw[M] = {cw[0][k], cw[1][k], cw[2][k], cw[3][k]};
+                const Re yv[M] = {cv[0][k], cv[1][k], cv[2][k], cv[3][k]};
+                Re xw[M], xv[M];
+                char_R(E, yw, xw);
+                char_R(E, yv, xv);
+                // momenta back to their places
+                PW[0][k] = xw[0]; PW[1][k] = xw[2]; PW[2][k] = xw[1]; PW[3][k] = xw[3];
+                PV[0][k] = xv[0]; PV[1][k] = xv[2]; PV[2][k] = xv[1]; PV[3][k] = xv[3];
+            }
             return;
         }
     }
