@@ -149,31 +149,31 @@ SHW_HD void stage2_order(int n, const Re am[M], const Re a0[M], const Re ap[M], 
                          Re w[M][3], Re lo[5][M], Re hi[5][M])
 {
     const bool proj = EQ == EULER && charpath && P.charwise;
-    // the data in characteristic fields (Euler, characteristic path)
-    Re cm[M], c0[M], cp[M], dm[M], dp[M];
-#pragma unroll
-    for (int c = 0; c < M; ++c) { cm[c] = am[c]; c0[c] = a0[c]; cp[c] = ap[c]; dm[c] = bm[c]; dp[c] = bp[c]; }
+    Re cq[M][5];
+    bool done = false;
     if constexpr (EQ == EULER) {
         if (proj) {
-            char_L(E, am, cm);
-            char_L(E, a0, c0);
-            char_L(E, ap, cp);
+            // Characteristic fields, centred as in 1D: the reconstruction
+            // commutes with adding a constant to the three values, so the
+            // fields of the neighbours' differences to this cell's value are
+            // reconstructed and the value is added back to the components'
+            // constant coefficient after R.
+            Re em[M], ep[M], cm[M], cp[M], dm[M], dp[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) { em[c] = am[c] - a0[c]; ep[c] = ap[c] - a0[c]; }
+            char_L(E, em, cm);
+            char_L(E, ep, cp);
             char_L(E, bm, dm);
             char_L(E, bp, dp);
-        }
-    }
-    Re cq[M][5];
+            const Re zero = 0.0;
 #pragma unroll
-    for (int f = 0; f < M; ++f) {
-        const Re xm = cm[f], x0 = c0[f], xp = cp[f], ym = dm[f], yp = dp[f];
-        big_quartic(xm, x0, xp, Re(dS * ym), Re(dS * yp), cq[f]);
-        if (full) {
-            if (n == 0) nonlinear_weights(cq[f], xm, x0, xp, P, w[f]);
-            combine(cq[f], xm, x0, xp, w[f], P);
-        }
-    }
-    if constexpr (EQ == EULER) {
-        if (proj) {
+            for (int f = 0; f < M; ++f) {
+                big_quartic(cm[f], zero, cp[f], Re(dS * dm[f]), Re(dS * dp[f]), cq[f]);
+                if (full) {
+                    if (n == 0) nonlinear_weights_jumps(cq[f], -cm[f], cp[f], P, w[f]);
+                    combine_centred(cq[f], -cm[f], cp[f], w[f], P);
+                }
+            }
             // back to the components on the five coefficients (R is linear:
             // the same polynomials as mapping the 2 (5 - n) edge jets)
 #pragma unroll
@@ -184,6 +184,19 @@ SHW_HD void stage2_order(int n, const Re am[M], const Re a0[M], const Re ap[M], 
                 char_R(E, y, x);
 #pragma unroll
                 for (int c = 0; c < M; ++c) cq[c][k] = x[c];
+            }
+#pragma unroll
+            for (int c = 0; c < M; ++c) cq[c][0] += a0[c];
+            done = true;
+        }
+    }
+    if (!done) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            big_quartic(am[c], a0[c], ap[c], Re(dS * bm[c]), Re(dS * bp[c]), cq[c]);
+            if (full) {
+                if (n == 0) nonlinear_weights(cq[c], am[c], a0[c], ap[c], P, w[c]);
+                combine(cq[c], am[c], a0[c], ap[c], w[c], P);
             }
         }
     }
