@@ -256,7 +256,10 @@ shw_status shw_get_tile(shw_ctx *ctx, int *variant);
 /* Autotuner: times `steps` CFL steps of every instance (no end time within
  * reach) for each tile variant, warm, on the context's own batch, keeps the
  * fastest (written to *best; per-variant milliseconds to ms[3], may be NULL)
- * and leaves state and times as they were.  d_scratch: caller-owned device
+ * and leaves state and times as they were.  In 1D a variant with more threads
+ * per instance within 3 % of the fastest is kept instead: the timed steps
+ * keep every instance busy, while a whole run ends on its longest instance,
+ * which more threads finish sooner.  d_scratch: caller-owned device
  * buffer of sum(shw_state_doubles) doubles for the saved state.  Steps
  * 1..100000.  Synchronising. */
 shw_status shw_autotune(shw_ctx *ctx, double *d_scratch, int steps, int *best, float *ms);

@@ -634,6 +634,7 @@ shw_status shw_autotune(shw_ctx *c, double *d_scratch, int steps, int *best, flo
     const int start = c->variant;
     float t_best = 0.0f;
     int v_best = start;
+    float t_v[N_TILE_VARIANTS] = {};
     for (int v = 0; v < N_TILE_VARIANTS && s == SHW_OK; ++v) {
         s = shw_set_tile(c, v);
         float t = 0.0f;
@@ -647,11 +648,22 @@ shw_status shw_autotune(shw_ctx *c, double *d_scratch, int steps, int *best, flo
         }
         if (s != SHW_OK) break;
         if (ms) ms[v] = t;
+        t_v[v] = t;
         if (v == 0 || t < t_best) {
             t_best = t;
             v_best = v;
         }
     }
+    // 1D: the probe keeps every instance busy, but a whole run ends on its
+    // longest instance, which finishes sooner the more threads advance it;
+    // so among the variants within 3 % of the fastest the one with the most
+    // threads per instance is kept
+    if (s == SHW_OK && c->dim == 1)
+        for (int v = N_TILE_VARIANTS - 1; v > v_best; --v)
+            if (t_v[v] <= 1.03f * t_best) {
+                v_best = v;
+                break;
+            }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     shw_status r = restore();
