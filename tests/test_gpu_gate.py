@@ -340,9 +340,10 @@ def test_trained_gate_keeps_the_2d_solution(trained, case):
 def test_gate_speeds_up_2d_runs(trained):
     """The point of the gate: on a 2D problem with shocks and smooth regions
     (four-quadrant, 512^2, 20 steps) the learned gate runs faster than the
-    plain scheme by at least 5%, best of three each (1.12x measured; 1.25x
-    before the plain 2D sweep's characteristic fields went to closed form,
-    which shrank the share of the work the gate saves)."""
+    plain scheme by at least 5%, best of three each (1.08x measured; 1.12x
+    before the plain path's stage 2 moved to coefficient-space projections,
+    1.25x before its characteristic fields went to closed form: each shrank
+    the share of the work the gate saves)."""
     import time
     params = trained[2]
     n = 512
