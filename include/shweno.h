@@ -152,12 +152,20 @@ shw_status shw_set_time(shw_ctx *ctx, const double *t);
 
 /* Step size from the CFL condition for every instance (host array of
  * n_inst): 1D dt = cfl dx / max_j(|u|+c); 2D dt = cfl / max_ij((|u|+c)/dx +
- * (|v|+c)/dy); scalar equations use |a| (advection) or |W| (Burgers).
- * Synchronising. */
+ * (|v|+c)/dy); scalar equations use |a| (advection) or |W| (Burgers); the
+ * maxima run over the cell averages at t_n.  The Courant number is the
+ * paper's (sec. 5 takes 0.9 for every run); the paper does not write the
+ * formula out, and these forms are a reading of it (in 2D the sum of the two
+ * directions' rates).  An instance whose averages are non-physical gets
+ * SHW_ENONPHYS.  Synchronising. */
 shw_status shw_compute_dt(shw_ctx *ctx, double *dt);
 
-/* One time step of every instance with the given step sizes (host array of
- * n_inst; entries <= 0 leave that instance alone).  Asynchronous. */
+/* One time step of every instance (the one-stage update of sec. 4, Steps
+ * 1-5: reconstruction, GRP at the interface points, the time-integrated
+ * fluxes of eq. (flux) / eq. (fx2d), and the update of the averages and the
+ * derivative averages) with the given step sizes (host array of n_inst;
+ * entries <= 0 leave that instance alone; a non-finite entry is SHW_EINVAL).
+ * Asynchronous. */
 shw_status shw_step(shw_ctx *ctx, const double *dt);
 
 /* One time step of every instance (sec. 4, Steps 1-5) with the step size its
@@ -167,10 +175,13 @@ shw_status shw_step(shw_ctx *ctx, const double *dt);
  * state stay stopped.  Synchronising; SHW_ENONPHYS as shw_advance_to. */
 shw_status shw_step_cfl(shw_ctx *ctx);
 
-/* Advance every instance i to time T[i] (host array) with device-computed CFL
- * steps, the last step of each instance clamped to end exactly at T[i];
- * at most max_steps steps per instance in this call.  Writes the number of
- * steps taken by each instance to steps_out (host array, may be NULL).
+/* Advance every instance i to time T[i] (host array) with steps of sec. 4
+ * whose sizes come from the CFL condition of shw_compute_dt, computed on the
+ * device from each step's own averages; the last step of each instance is
+ * clamped to end exactly at T[i] (a reading: the paper's runs of sec. 5 stop
+ * at their end times without saying how the last step is taken).  At most
+ * max_steps steps per instance in this call.  Writes the number of steps
+ * taken by each instance to steps_out (host array, may be NULL).
  * Synchronising; returns SHW_ENONPHYS if any instance went non-physical. */
 shw_status shw_advance_to(shw_ctx *ctx, const double *T, long long max_steps,
                           long long *steps_out);

@@ -20,6 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_FMA_PATH = os.path.join(_HERE, "liboracle_fma.so")
 _SOURCES = ["recon.c", "riemann.c", "ck.c", "step.c", "mlp.c"]
 
 ADVECTION, BURGERS, EULER = 0, 1, 2
@@ -27,18 +28,25 @@ BC_PERIODIC, BC_TRANSMISSIVE, BC_REFLECTIVE = 0, 1, 2
 W_NONLINEAR, W_LINEAR, W_GATED = 0, 1, 2
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, contracted: bool = False) -> str:
     """Compile the oracle into oracle/liboracle.so with gcc (strict FP64:
-    no contraction into FMA, so the oracle's rounding is plain)."""
+    no contraction into FMA, so the oracle's rounding is plain).
+
+    contracted: build the same sources into liboracle_fma.so with every
+    contractible a * b + c fused into one FMA instead.  That library computes
+    the same arithmetic in another rounding order; the tests use it only to
+    measure how much two valid roundings of the scheme can differ."""
     srcs = [os.path.join(_HERE, s) for s in _SOURCES if os.path.exists(os.path.join(_HERE, s))]
-    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+    path = _FMA_PATH if contracted else _LIB_PATH
+    fp = ["-mfma", "-ffp-contract=fast"] if contracted else ["-ffp-contract=off"]
+    cmd = ["gcc", "-O2", "-std=c11", *fp, "-fno-fast-math",
            "-fPIC", "-shared", "-Wall", "-Wno-unused-function", "-fopenmp",
-           "-o", _LIB_PATH + ".tmp"] + srcs + ["-lm"]
+           "-o", path + ".tmp"] + srcs + ["-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
-    return _LIB_PATH
+    os.replace(path + ".tmp", path)
+    return path
 
 
 class _Cfg(ctypes.Structure):
@@ -77,17 +85,19 @@ class Config:
         return s
 
 
-_lib = None
+_libs = {}
 _D = ctypes.POINTER(ctypes.c_double)
 _U8 = ctypes.POINTER(ctypes.c_uint8)
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build()
-        L = ctypes.CDLL(_LIB_PATH)
+def lib(contracted: bool = False):
+    """The strict oracle library, or (contracted=True) its FMA-contracted
+    build, loaded once each."""
+    if contracted not in _libs:
+        path = _FMA_PATH if contracted else _LIB_PATH
+        if not os.path.exists(path):
+            build(contracted=contracted)
+        L = ctypes.CDLL(path)
         P = ctypes.POINTER(_Cfg)
         L.orc_ncomp.argtypes = [ctypes.c_int, ctypes.c_int]
         L.orc_big_quartic.argtypes = [_D, _D, _D]
@@ -127,8 +137,8 @@ def lib():
                                           ctypes.c_int, _D]
         L.orc_gate_label1d.argtypes = [P, ctypes.c_int, ctypes.c_double, _D, ctypes.c_int,
                                        ctypes.c_double]
-        _lib = L
-    return _lib
+        _libs[contracted] = L
+    return _libs[contracted]
 
 
 def _p(a: np.ndarray):
@@ -311,22 +321,24 @@ def dt2d(cfg: Config, state, dx, dy, cfl) -> float:
     return lib().orc_dt2d(ctypes.byref(cfg.c()), nx, ny, dx, dy, cfl, _p(st))
 
 
-def step1d(cfg: Config, state, dx, dt, flags=None):
-    """state: (2, m, n).  Returns (new_state, nonphysical_flag)."""
+def step1d(cfg: Config, state, dx, dt, flags=None, contracted=False):
+    """state: (2, m, n).  Returns (new_state, nonphysical_flag).
+    contracted: run the FMA-contracted build (another rounding order)."""
     st = _f64(state)
     out = np.empty_like(st)
     f, fp = _flags(flags, st.shape[-1])
-    bad = lib().orc_step1d(ctypes.byref(cfg.c()), st.shape[-1], dx, dt, _p(st), _p(out), fp)
+    bad = lib(contracted).orc_step1d(ctypes.byref(cfg.c()), st.shape[-1], dx, dt, _p(st), _p(out), fp)
     return out, bool(bad)
 
 
-def step2d(cfg: Config, state, dx, dy, dt, flags=None):
-    """state: (4, m, ny, nx).  Returns (new_state, nonphysical_flag)."""
+def step2d(cfg: Config, state, dx, dy, dt, flags=None, contracted=False):
+    """state: (4, m, ny, nx).  Returns (new_state, nonphysical_flag).
+    contracted: run the FMA-contracted build (another rounding order)."""
     st = _f64(state)
     out = np.empty_like(st)
     ny, nx = st.shape[-2:]
     f, fp = _flags(flags, nx * ny)
-    bad = lib().orc_step2d(ctypes.byref(cfg.c()), nx, ny, dx, dy, dt, _p(st), _p(out), fp)
+    bad = lib(contracted).orc_step2d(ctypes.byref(cfg.c()), nx, ny, dx, dy, dt, _p(st), _p(out), fp)
     return out, bool(bad)
 
 

@@ -613,7 +613,13 @@ shw_status shw_autotune(shw_ctx *c, double *d_scratch, int steps, int *best, flo
     size_t nd = 0;
     for (const auto &m : c->meshes) nd += state_doubles(&m, c->params.eq);
     std::vector<InstState> saved;
+    std::vector<int> saved_bad(c->n_inst);
     shw_status s = read_ist(c, saved);
+    // the per-instance non-physical flags (2D reads them at the next step)
+    if (s == SHW_OK)
+        s = c->hip(hipMemcpyAsync(saved_bad.data(), c->ws + c->lay.bad, c->n_inst * sizeof(int),
+                                  hipMemcpyDeviceToHost, c->stream), "save flags");
+    if (s == SHW_OK) s = c->hip(hipStreamSynchronize(c->stream), "save flags sync");
     if (s == SHW_OK)
         s = c->hip(hipMemcpyAsync(d_scratch, c->state, nd * sizeof(double), hipMemcpyDeviceToDevice,
                                   c->stream), "save state");
@@ -624,6 +630,9 @@ shw_status shw_autotune(shw_ctx *c, double *d_scratch, int steps, int *best, flo
         if (r == SHW_OK)
             r = c->hip(hipMemcpyAsync(c->ist(), saved.data(), c->n_inst * sizeof(InstState),
                                       hipMemcpyHostToDevice, c->stream), "restore times");
+        if (r == SHW_OK)
+            r = c->hip(hipMemcpyAsync(c->ws + c->lay.bad, saved_bad.data(), c->n_inst * sizeof(int),
+                                      hipMemcpyHostToDevice, c->stream), "restore flags");
         return r;
     };
     // every instance steps: no end time within reach

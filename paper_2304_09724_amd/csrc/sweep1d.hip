@@ -102,11 +102,12 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
             // the nonlinear weights only if a cell flagged then lies within 2s
             // cells (its reconstruction reads its neighbours, and each step
             // updates a cell from the reconstructions next to it); a ghost
-            // cell stands for the cell it copies
+            // cell stands for the cell it copies, window included
             const int reach = 2 * gate_since;
+            const int home = flag_cell(jl, n, d.bc_lo, d.bc_hi);
             unsigned any = 0;
             for (int o = -reach; o <= reach; ++o)
-                any |= flags[d.cell_off + flag_cell(jl + o, n, d.bc_lo, d.bc_hi)];
+                any |= flags[d.cell_off + flag_cell(home + o, n, d.bc_lo, d.bc_hi)];
             full = any != 0;
         }
         double lo[5][M], hi[5][M];
@@ -128,8 +129,10 @@ __device__ __forceinline__ bool sweep_instance(const Inst1D &d, const double *__
             for (int c = 0; c < M; ++c) { Fh[c] = 0.0; We[c] = 0.0; }
         }
         if constexpr (GUARD) {
-            if (lane >= 1 && lane <= CHUNK && j >= 0 && j <= n) {
-                // the safeguard's record of face j - 1/2 (each face once)
+            if (lane >= 1 && (lane <= CHUNK || j == n) && j >= 0 && j <= n) {
+                // the safeguard's record of face j - 1/2 (each face once:
+                // lanes 1..62, and the last face of the instance from lane 63
+                // when n is a multiple of 62)
 #pragma unroll
                 for (int c = 0; c < M; ++c) {
                     faces[c * (n + 1) + j] = Fh[c];

@@ -1,8 +1,10 @@
 """Training of the learned troubled-cell gate on the GPU.
 
 Data come from the method itself: plain (nonlinear-weight) runs of 1D Euler
-problems are stopped at several times and every cell contributes its 8
-features and its label (whether the nonlinear weights depart from the linear
+problems are stopped at several times and every cell contributes its 16
+features (per conservative component the normalised shape of the jumps its
+reconstruction reads and their size, and the normal Mach-like ratio
+u / (|u| + c)) and its label (whether the nonlinear weights depart from the linear
 ones), both computed by the library's kernels.  Training runs the library's
 FP32 forward/backward kernel and its Adam kernel; this module only drives the
 loop.

@@ -182,6 +182,40 @@ def test_positivity_safeguard_blast_waves():
         assert rel_err(s.get_state(i), o) < TOL, ns[i]
 
 
+@pytest.mark.parametrize("inst,n,cell", [(9, 124, 123), (140, 124, 122), (9, 248, 247)])
+def test_positivity_safeguard_next_to_the_right_end(inst, n, cell):
+    """A troubled cell next to the right end of an instance whose size is a
+    multiple of the 62-cell chunk (the last face then falls on the chunk's top
+    lane): Riemann data of the batch with the jump moved to cell edge `cell`,
+    transmissive ends; the oracle's run with the same safeguard is the
+    reference.  The oracle's first repaired step has cell n-2 troubled and
+    cell n-1 not, so the repair of cell n-1 reads the record of the last face."""
+    d = WL.riemann_batch_1d(count=4096, T=0.14)[inst]
+    st = WL.riemann_1d(n, d.left, d.right, 0.0, 1.0, cell / n)
+    cfg = O.Config(eq=O.EULER, bc=(O.BC_TRANSMISSIVE,) * 4)
+    x, hit = st, None
+    for k in range(4):                   # the precondition, on the oracle alone
+        dt = O.dt1d(cfg, x, 1.0 / n, 0.9)
+        y, bad = O.step1d(cfg, x, 1.0 / n, dt)
+        if bad:
+            rho, m, E = y[0]
+            ok = np.isfinite(y[0]).all(axis=0) & (rho > 0) & (0.4 * (E - 0.5 * m * m / rho) > 0)
+            hit = (not ok[n - 2]) and ok[n - 1]
+            break
+        x = y
+    assert hit, "no repair next to the right end"
+    T = 0.03
+    s = S.Solver([S.Mesh.line(n, 0.0, 1.0, S.BC_TRANSMISSIVE)],
+                 S.Params.make(eq=S.EULER, positivity=True))
+    s.set_state(0, st)
+    steps = s.advance_to(T, raise_nonphysical=False)
+    o, t, osteps, bad = O.advance1d(O.Config(eq=O.EULER, bc=(O.BC_TRANSMISSIVE,) * 4,
+                                             positivity=True), st, 1.0 / n, 0.9, T)
+    assert (s.instance_status()[0] != 0) == bool(bad) and steps[0] == osteps
+    if not bad:
+        assert rel_err(s.get_state(0), o) < TOL
+
+
 def test_positivity_safeguard_leaves_other_runs_unchanged():
     """A ragged Riemann batch that never needs the safeguard: bit for bit the
     same states with it on and off."""

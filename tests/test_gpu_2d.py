@@ -399,3 +399,34 @@ def test_tile_variants_and_autotuner():
         assert np.array_equal(s.get_state(i), before[i])
     # and it keeps stepping as before
     s.advance_to(0.04, raise_nonphysical=False)
+
+
+def test_autotuner_restores_nonphysical_flags():
+    """An instance that turns non-physical during the autotuner's probe steps
+    (a four-quadrant problem that fails at its fourth step on 24^2 cells) is
+    restored with its state: afterwards the batch steps bit for bit as a
+    fresh context with the same tile does, and nothing is reported."""
+    bad_quads = WL.four_quadrant_batch(count=16, seed=11)[12].quads
+    ok_quads = WL.four_quadrant_batch(count=3, seed=11)[1].quads
+    sizes = [46, 24]
+    meshes = [S.Mesh.rect(n, n, 0.0, 1.0, 0.0, 1.0, S.BC_TRANSMISSIVE, S.BC_TRANSMISSIVE)
+              for n in sizes]
+    states = [WL.four_quadrant(46, ok_quads), WL.four_quadrant(24, bad_quads)]
+    o = O.advance2d(O.Config(eq=O.EULER, bc=(O.BC_TRANSMISSIVE,) * 4), states[1], 1 / 24, 1 / 24,
+                    0.9, 10.0, max_steps=8)
+    assert o[3] and 2 < o[2] < 8                  # fails inside the probe, not before
+    runs = []
+    for tune in (True, False):
+        s = S.Solver(meshes, gparams())
+        for i, st in enumerate(states):
+            s.set_state(i, st)
+        if tune:
+            best, _ = s.autotune(steps=8)
+            assert np.all(s.instance_status() == 0)
+        else:
+            s.set_tile(best)
+        steps = s.advance_to(10.0, max_steps=2, raise_nonphysical=False)
+        assert np.array_equal(steps, [2, 2]) and np.all(s.instance_status() == 0)
+        runs.append([s.get_state(i) for i in range(2)])
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)

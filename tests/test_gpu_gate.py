@@ -229,6 +229,82 @@ def test_trained_gate_keeps_the_error_of_the_plain_method(trained, every):
     assert (passed & lv).sum() <= 0.05 * lv.sum()
 
 
+def widen(flags, r, periodic):
+    """A cell counts as flagged if a flagged cell lies within r cells of it
+    (beyond a non-periodic end the window stops at the end cell)."""
+    n = flags.size
+    out = np.zeros(n, dtype=bool)
+    for o in range(-r, r + 1):
+        if periodic:
+            out |= np.roll(flags, -o).astype(bool)
+        else:
+            idx = np.clip(np.arange(n) + o, 0, n - 1)
+            out |= flags[idx].astype(bool)
+    return out.astype(np.uint8)
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_learned_gate_1d_steps_match_the_oracle(trained, periodic):
+    """The benchmark's 1D gate configuration (threshold 0.05, a gate pass every
+    3 steps) on a ragged batch, element by element against the oracle: the
+    batch advances 3 steps per call, so each call opens with a gate pass; the
+    decisions that pass stored (read back with shw_get_flags) are widened by
+    2s cells for the s-th step after it, and the oracle takes that step in its
+    GATED mode with the widened flags (a ghost cell takes the decision of the
+    cell it copies).  Relative L-infinity per quantity <= 1e-11 after 12
+    steps."""
+    X, y, params, hist = trained
+    K, calls = 3, 4
+    insts = WL.riemann_batch_1d(count=8, seed=77, nmin=60, nmax=400)
+    if periodic:
+        # a smooth wave with a jump in it: the gate meets both kinds of cell
+        states = []
+        for d in insts:
+            st = WL.density_wave_1d(d.n, x0=0.0, x1=1.0, k=2).copy()
+            st[:, :, d.n // 3:] = d.state()[:, :, d.n // 3:]
+            states.append(st)
+        bc, obc = S.BC_PERIODIC, O.BC_PERIODIC
+    else:
+        states = [d.state() for d in insts]
+        bc, obc = S.BC_TRANSMISSIVE, O.BC_TRANSMISSIVE
+    meshes = [S.Mesh.line(d.n, d.x0, d.x1, bc) for d in insts]
+    g = S.Solver(meshes, S.Params.make(eq=S.EULER, weights=S.W_LEARNED, gate_threshold=0.05,
+                                       gate_every=K))
+    g.gate_load(params)
+    for i, st in enumerate(states):
+        g.set_state(i, st)
+    cfg_dt = O.Config(eq=O.EULER, bc=(obc,) * 4)
+    cfg = O.Config(eq=O.EULER, bc=(obc,) * 4, weights=O.W_GATED)
+    ost = [st.copy() for st in states]
+    obad = [False] * len(insts)
+    mixed = widened_differs = 0
+    for _ in range(calls):
+        steps = g.advance_to(np.full(len(insts), 10.0), max_steps=K, raise_nonphysical=False)
+        for i, d in enumerate(insts):
+            if obad[i]:
+                continue
+            f = g.get_flags(i)
+            mixed += int(0 < f.mean() < 1)
+            for s_ in range(K):
+                w = widen(f, 2 * s_, periodic)
+                widened_differs += int(not np.array_equal(w, f))
+                dt = O.dt1d(cfg_dt, ost[i], d.dx, 0.9)
+                ost[i], bad = O.step1d(cfg, ost[i], d.dx, dt, w)
+                if bad:
+                    obad[i] = True
+                    break
+    codes = g.instance_status()
+    compared = 0
+    for i in range(len(insts)):
+        assert (codes[i] != 0) == obad[i], i
+        if not obad[i]:
+            go = g.get_state(i)
+            err = max(np.abs(go[q] - ost[i][q]).max() / np.abs(ost[i][q]).max() for q in range(2))
+            assert err < 1e-11, (i, err)
+            compared += 1
+    assert compared >= 5 and mixed >= 5 and widened_differs > 0
+
+
 # ---- 2D --------------------------------------------------------------------
 
 QUADS = [(1.5, 0.0, 0.0, 1.5), (0.5323, 1.206, 0.0, 0.3), (0.138, 1.206, 1.206, 0.029),

@@ -83,6 +83,63 @@ def test_hllc_state_consistency():
     np.testing.assert_allclose(O.hllc_state(G, W, W), W, rtol=1e-14)
 
 
+def prim(W, g=G):
+    """(rho, u, v, p) of a conservative state (v = 0 in 1D)."""
+    rho, E = W[0], W[-1]
+    u = W[1] / rho
+    v = W[2] / rho if W.size == 4 else 0.0
+    return rho, u, v, (g - 1) * (E - 0.5 * rho * (u * u + v * v))
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+def test_hllc_star_state_meets_the_jump_conditions(dim):
+    """The HLLC state of the leading term (sec. 2.1, Toro ch. 10) on random
+    data, both star regions: with S* = (rho u)*/rho* and Davis' speeds S_L,
+    S_R, the state U*_K on the side K of the contact satisfies the
+    Rankine-Hugoniot condition across S_K with the flux of a state moving at
+    S* under the pressure p*_K = p_K + rho_K (S_K - u_K)(S* - u_K):
+    F(U_K) + S_K (U*_K - U_K) = S* U*_K + p*_K (0, 1, [0,] S*); the pressures
+    p*_L and p*_R agree (the condition that fixes S*); the transverse velocity
+    is side K's; the energy term (S* - u_K), which vanishes at a contact, is
+    exercised because S* != u_K on this data."""
+    rng = np.random.default_rng(31 + dim)
+    seen = {"L": 0, "R": 0}
+    for _ in range(400):
+        rl, rr, pl, pr = rng.uniform(0.1, 2.0, 4)
+        ul, ur, vl, vr = rng.uniform(-2.0, 2.0, 4)
+        if dim == 1:
+            WL, WR = prim_to_cons(rl, ul, pl), prim_to_cons(rr, ur, pr)
+        else:
+            WL, WR = prim_to_cons(rl, ul, pl, vl), prim_to_cons(rr, ur, pr, vr)
+        Ws = O.hllc_state(G, WL, WR)
+        cl, cr = np.sqrt(G * pl / rl), np.sqrt(G * pr / rr)
+        SL, SR = min(ul - cl, ur - cr), max(ul + cl, ur + cr)
+        if SL >= 0:
+            np.testing.assert_array_equal(Ws, WL)
+            continue
+        if SR < 0:
+            np.testing.assert_array_equal(Ws, WR)
+            continue
+        Ss = Ws[1] / Ws[0]
+        K = "L" if Ss >= 0 else "R"
+        seen[K] += 1
+        WK, SK = (WL, SL) if K == "L" else (WR, SR)
+        rk, uk, vk, pk = prim(WK)
+        p_star = {k: p + r * (S - u) * (Ss - u)
+                  for k, (r, u, p, S) in {"L": (rl, ul, pl, SL), "R": (rr, ur, pr, SR)}.items()}
+        assert p_star["L"] == pytest.approx(p_star["R"], rel=1e-11, abs=1e-12)
+        ps = p_star[K]
+        D = np.zeros(WK.size)
+        D[1], D[-1] = 1.0, Ss
+        lhs = flux(WK) + SK * (Ws - WK)
+        rhs = Ss * Ws + ps * D
+        np.testing.assert_allclose(lhs, rhs, rtol=1e-11, atol=1e-11 * np.abs(flux(WK)).max())
+        assert Ws[0] == pytest.approx(rk * (SK - uk) / (SK - Ss), rel=1e-13)
+        if dim == 2:
+            assert Ws[2] / Ws[0] == pytest.approx(vk, rel=1e-12, abs=1e-14)
+    assert seen["L"] > 50 and seen["R"] > 50
+
+
 # ---- HLLE (the positivity safeguard's first-order flux) ----------------------
 
 def einfeldt_bounds(WL, WR, g=G):

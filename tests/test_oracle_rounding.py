@@ -1,0 +1,61 @@
+"""How far two valid rounding orders of the same scheme drift apart: the
+oracle as built (no contraction) against the same source built with every
+a * b + c contracted into an FMA, on windows of the 1024^2 density wave (sec.
+5, the 2D accuracy example) stepped 20 times.  Per plane (relative to the
+plane's largest value over the mesh) the cell averages agree to a few ulps,
+while the derivative averages V, Y and above all Z, formed as differences of
+edge and corner values divided by dx, dy and dx dy (sec. 3.3), differ far
+beyond 1e-11.  This is the floor the full-size GPU bounds stand on
+(tests/tolerances.py): each bound must lie above it by a stated factor, and
+the floor of Z must exceed 1e-11 by an order of magnitude, or a per-plane
+1e-11 would have been attainable."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2304_09724_amd import workloads as WL
+from tests.tolerances import FLOOR_SHARE, FULL_2D
+
+
+def window(st, i, j, r):
+    n = st.shape[-1]
+    ii, jj = np.arange(i - r, i + r + 1) % n, np.arange(j - r, j + r + 1) % n
+    return np.ascontiguousarray(st[:, :, jj][:, :, :, ii])
+
+
+@pytest.fixture(scope="module")
+def floor():
+    n, k = 1024, 20
+    st = WL.density_wave_2d(n)
+    cfg = O.Config(eq=O.EULER)
+    h = 2.0 / n
+    dt = O.dt2d(cfg, st, h, h, 0.9)
+    r = 2 * k + 1
+    # scales of the whole mesh, as the GPU tests take them (a window's own
+    # edges hold no valid data after the steps)
+    scale = np.abs(st).max(axis=(-1, -2))
+    scale[:, 1:3] = np.sqrt(st[:, 1] ** 2 + st[:, 2] ** 2).max(axis=(-1, -2))[:, None]
+    worst = np.zeros(4)
+    for i, j in [(3, 1022), (1023, 1023)]:      # two of the GPU test's cells
+        a = b = window(st, i, j, r)
+        for _ in range(k):
+            a, _ = O.step2d(cfg, a, h, h, dt)
+            b, _ = O.step2d(cfg, b, h, h, dt, contracted=True)
+        d = np.abs(a[:, :, r, r] - b[:, :, r, r]) / scale
+        worst = np.maximum(worst, d.max(axis=1))
+    print("strict vs contracted, per quantity W V Y Z:", worst)
+    return dict(zip("WVYZ", worst))
+
+
+def test_cell_averages_agree_to_rounding(floor):
+    assert floor["W"] < 1e-13
+
+
+def test_corner_derivative_floor_exceeds_1e11(floor):
+    assert floor["Z"] > 1e-9
+    assert floor["V"] > 3e-12 and floor["Y"] > 3e-12
+
+
+@pytest.mark.parametrize("q", "WVYZ")
+def test_full_size_bounds_sit_above_the_floor(floor, q):
+    assert floor[q] <= FLOOR_SHARE * FULL_2D[q]

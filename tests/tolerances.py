@@ -1,0 +1,26 @@
+"""Parity tolerances of the GPU tests against the oracle (relative L-infinity:
+max |gpu - oracle| over a plane, divided by the largest |value| of that plane;
+the two momentum components of a quantity share one scale, the largest
+momentum magnitude, since a component that starts at zero has no size of its
+own).
+
+Cell averages W are held to 1e-11 everywhere.  The derivative averages of 2D
+are differences of edge values (V, Y) or of corner values (Z) divided by dx,
+dy or dx dy (sec. 3.3): the rounding of those values is relative to W, and the
+division lifts it by 1/dx or 1/(dx dy) relative to the derivative's own size.
+Two valid rounding orders of the oracle itself (the strict build and its
+FMA-contracted build, same source) differ on 1024^2 density-wave windows
+after 20 steps by up to about 7e-12 on V and Y and 2e-9 on Z per plane
+(tests/test_oracle_rounding.py measures and pins this floor), so 1e-11 per
+plane is out of reach there for any implementation that rounds in another
+order; the full-size bounds below sit a stated factor above that floor.
+Small meshes (up to a few hundred cells a side, a few steps) keep 1e-11 for
+every quantity."""
+
+TOL = 1e-11
+
+# full-size 2D windows (20 steps), per quantity W, V, Y, Z
+FULL_2D = {"W": 1e-11, "V": 2e-10, "Y": 2e-10, "Z": 1e-7}
+
+# the measured oracle-vs-oracle floor may not exceed this share of each bound
+FLOOR_SHARE = 0.2
