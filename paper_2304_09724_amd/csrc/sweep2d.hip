@@ -235,15 +235,16 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
 #pragma unroll
         for (int n = 0; n <= 4; ++n) {
             double am[M], a0[M], ap[M], bm[M], bp[M];
+            // a compiler barrier: this order's coefficients are read from the
+            // LDS here, not held in registers from an earlier order
+            asm volatile("" ::: "memory");
 #pragma unroll
             for (int c = 0; c < M; ++c) {
-                // volatile: re-read per order rather than held in registers
-                const volatile double *vp = &s_poly[0][0][0][0];
                 double pw[5], pv[5];
 #pragma unroll
                 for (int k = 0; k < 5; ++k) {
-                    pw[k] = vp[((0 * M + c) * 5 + k) * NB + threadIdx.x];
-                    pv[k] = vp[((1 * M + c) * 5 + k) * NB + threadIdx.x];
+                    pw[k] = s_poly[0][c][k][threadIdx.x];
+                    pv[k] = s_poly[1][c][k][threadIdx.x];
                 }
                 const double A = deriv_at(pw, node[g], n, sct[n]);
                 const double B = deriv_at(pv, node[g], n, sct[n]);

@@ -20,7 +20,7 @@ every quantity."""
 TOL = 1e-11
 
 # full-size 2D windows (20 steps), per quantity W, V, Y, Z
-FULL_2D = {"W": 1e-11, "V": 2e-10, "Y": 2e-10, "Z": 1e-7}
+FULL_2D = {"W": 1e-11, "V": 1e-10, "Y": 1e-10, "Z": 2e-8}
 
 # the measured oracle-vs-oracle floor may not exceed this share of each bound
 FLOOR_SHARE = 0.2
