@@ -47,7 +47,8 @@ typedef enum {
     SHW_ENOMEM = -2,     /* host allocation failed */
     SHW_EDEVICE = -3,    /* a HIP call failed */
     SHW_ENONPHYS = -4,   /* a non-physical state was detected */
-    SHW_ESTATE = -5      /* call made in the wrong state (e.g. gate not loaded) */
+    SHW_ESTATE = -5,     /* call made in the wrong state (e.g. gate not loaded) */
+    SHW_ESCRATCH = -6    /* the batch exceeds the static scratch of shw_advance1d_static */
 } shw_status;
 
 enum { SHW_ADVECTION = 0, SHW_BURGERS = 1, SHW_EULER = 2 };
@@ -285,6 +286,42 @@ shw_status shw_status_detail(shw_ctx *ctx, int *bad_instance, char *msg, size_t 
 
 /* Library version string. */
 const char *shw_version(void);
+
+/* ---- an entry point that allocates nothing --------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * shw_advance1d_static: the batched 1D time loop of shw_create +
+ * shw_advance_to + shw_destroy (the same kernels; the same states and step
+ * counts bit for bit), with every device buffer beyond the caller's state
+ * (the ping-pong copy of the state, the instance descriptors and time-loop
+ * state, the work counter; with the positivity safeguard its face records
+ * and per-cell flags) carved out of a static array the library keeps on each
+ * GPU it runs on: SHW_STATIC_SCRATCH_BYTES per GPU, held until the process
+ * ends.  The call allocates no device or host memory (no hipMalloc or
+ * hipFree, no heap allocation).
+ *   meshes, n_inst, params: as shw_create, 1D only, weights NONLINEAR or
+ *     LINEAR (no per-cell flags, no learned gate); at most
+ *     SHW_STATIC_MAX_INSTANCES instances;
+ *   d_state: the caller's device state (layout as above), taken as the state
+ *     at t = 0 of every instance and advanced in place;
+ *   T: host array of end times; each instance takes CFL steps to T[i], the
+ *     last one clamped (as shw_advance_to), at most max_steps of them;
+ *   steps_out: host array of the steps taken per instance (may be NULL);
+ *   hip_stream: the stream the work is queued on (NULL = default).
+ * Returns SHW_ESCRATCH, before any device work, if the batch's buffers exceed
+ * SHW_STATIC_SCRATCH_BYTES or n_inst exceeds SHW_STATIC_MAX_INSTANCES;
+ * SHW_EINVAL for other invalid arguments; SHW_ENONPHYS if an instance met a
+ * non-physical state (that instance stopped there, steps_out is written);
+ * SHW_EDEVICE if a HIP call failed.  Synchronising.  Every call on a GPU
+ * uses that GPU's one array and keeps no state from an earlier call: calls
+ * that overlap on one GPU (other threads or streams) race and must be
+ * serialised by the caller. */
+#define SHW_STATIC_SCRATCH_BYTES (64u << 20)
+#define SHW_STATIC_MAX_INSTANCES 4096
+shw_status shw_advance1d_static(const shw_mesh *meshes, int n_inst, const shw_params *params,
+                                double *d_state, const double *T, long long max_steps,
+                                long long *steps_out, void *hip_stream);
 
 #ifdef __cplusplus
 }

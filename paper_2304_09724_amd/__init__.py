@@ -22,7 +22,7 @@ W_NONLINEAR, W_LINEAR, W_GATED, W_LEARNED = 0, 1, 2, 3
 GATE_NFEATURES = 16
 GATE_NPARAMS = 1633
 STATUS = {0: "SHW_OK", -1: "SHW_EINVAL", -2: "SHW_ENOMEM", -3: "SHW_EDEVICE",
-          -4: "SHW_ENONPHYS", -5: "SHW_ESTATE"}
+          -4: "SHW_ENONPHYS", -5: "SHW_ESTATE", -6: "SHW_ESCRATCH"}
 
 
 class ShwError(RuntimeError):
@@ -112,6 +112,8 @@ def lib():
                                    ctypes.POINTER(ctypes.c_float)]
         L.shw_status_detail.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.c_char_p,
                                         ctypes.c_size_t]
+        L.shw_advance1d_static.argtypes = [MP, ctypes.c_int, PP, vp, _D, ctypes.c_longlong,
+                                           _LL, vp]
         _lib = L
     return _lib
 
@@ -170,6 +172,28 @@ def mlp_grad(X, y, params, pos_weight=1.0):
 def mlp_adam(params, grad, m, v, step, lr):
     _check_free(lib().shw_mlp_adam(_vp(params), _vp(grad), _vp(m), _vp(v), step, lr,
                                    _stream_ptr()), "mlp_adam")
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+STATIC_MAX_INSTANCES = 4096
+
+
+def advance1d_static(meshes, params, state, T, max_steps=1_000_000, raise_nonphysical=True):
+    """shw_advance1d_static: advance a 1D batch (state: cuda float64 tensor of
+    the instances' states back to back, taken at t = 0) to the end times T in
+    place, with the library's static scratch and no allocation.  Returns the
+    steps per instance."""
+    import torch
+    n = len(meshes)
+    assert state.dtype == torch.float64 and state.is_contiguous() and state.is_cuda
+    arr = (Mesh * n)(*meshes)
+    T = np.ascontiguousarray(np.broadcast_to(np.asarray(T, float), (n,)))
+    steps = np.zeros(n, dtype=np.int64)
+    code = lib().shw_advance1d_static(arr, n, ctypes.byref(params), _vp(state), _dptr(T),
+                                      max_steps, steps.ctypes.data_as(_LL), _stream_ptr())
+    if code != 0 and not (code == -4 and not raise_nonphysical):
+        raise ShwError(code, "advance1d_static")
+    return steps
 
 
 class Solver:
