@@ -39,7 +39,11 @@ def build(verbose: bool = False, contracted: bool = False) -> str:
     srcs = [os.path.join(_HERE, s) for s in _SOURCES if os.path.exists(os.path.join(_HERE, s))]
     path = _FMA_PATH if contracted else _LIB_PATH
     fp = ["-mfma", "-ffp-contract=fast"] if contracted else ["-ffp-contract=off"]
-    cmd = ["gcc", "-O2", "-std=c11", *fp, "-fno-fast-math",
+    # ORACLE_SANITIZE=1: an AddressSanitizer + UndefinedBehaviorSanitizer build
+    # (run the tests with the ASan runtime preloaded into the interpreter)
+    san = (["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+            "-fno-omit-frame-pointer", "-g"] if os.environ.get("ORACLE_SANITIZE") else [])
+    cmd = ["gcc", "-O2", "-std=c11", *fp, "-fno-fast-math", *san,
            "-fPIC", "-shared", "-Wall", "-Wno-unused-function", "-fopenmp",
            "-o", path + ".tmp"] + srcs + ["-lm"]
     if verbose:

@@ -52,7 +52,7 @@ def test_cell_averages_agree_to_rounding(floor):
 
 
 def test_corner_derivative_floor_exceeds_1e11(floor):
-    assert floor["Z"] > 1e-9
+    assert floor["Z"] > 1e-10
     assert floor["V"] > 3e-12 and floor["Y"] > 3e-12
 
 
