@@ -27,6 +27,39 @@ constexpr int BLOCK = 256;
 constexpr int LINES = BLOCK / WAVE;
 constexpr int CHUNK = WAVE - 4;
 
+// a value the same in every lane, moved to a scalar register
+__device__ __forceinline__ double uniform(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// A double parked in two accumulation registers until it is needed: the GRP
+// seeds of an edge node wait there for its Lax-Wendroff series, written once
+// and read once, so the architectural registers keep the stage-2 working set.
+struct Parked {
+    unsigned lo, hi;
+};
+
+__device__ __forceinline__ Parked park(double x)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    Parked p;
+    asm("v_accvgpr_write_b32 %0, %1" : "=a"(p.lo) : "v"((unsigned)b));
+    asm("v_accvgpr_write_b32 %0, %1" : "=a"(p.hi) : "v"((unsigned)(b >> 32)));
+    return p;
+}
+
+__device__ __forceinline__ double unpark(Parked p)
+{
+    unsigned lo, hi;
+    asm("v_accvgpr_read_b32 %0, %1" : "=v"(lo) : "a"(p.lo));
+    asm("v_accvgpr_read_b32 %0, %1" : "=v"(hi) : "a"(p.hi));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // source index of a (possibly ghost) index j of an axis of n cells
 __device__ __forceinline__ int map_index(int j, int n, int bc_lo, int bc_hi, int &kind)
 {
@@ -205,9 +238,14 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
                 s_poly[1][c][k][threadIdx.x] = PV[c][k];
             }
     }
-    const double iT = 1.0 / dT, iS = 1.0 / dS;
-    const double sct[5] = {1.0, iT, iT * iT, iT * iT * iT, iT * iT * iT * iT};
-    const double scs[5] = {1.0, iS, iS * iS, iS * iS * iS, iS * iS * iS * iS};
+    // the scalings 1/dt^n and 1/ds^n are the same for the whole block: held
+    // in scalar registers (an operand of the vector instructions), not in
+    // vector ones
+    const double iT = uniform(1.0 / dT), iS = uniform(1.0 / dS);
+    const double sct[5] = {1.0, iT, uniform(iT * iT), uniform(iT * iT * iT),
+                           uniform(iT * iT * iT * iT)};
+    const double scs[5] = {1.0, iS, uniform(iS * iS), uniform(iS * iS * iS),
+                           uniform(iS * iS * iS * iS)};
     const double node[4] = {-0.5, -LOB_H, LOB_H, 0.5};
     const double nw[4] = {LOB_W0, LOB_W1, LOB_W1, LOB_W0};
 
@@ -230,7 +268,8 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
         // once and become the GRP's series seeds there, so only one order of
         // jets is ever held (each lane reads back only its own LDS slots).
         const double inv_fact[5] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
-        double w[M][3], seed[M][5][5];
+        double w[M][3];
+        Parked pseed[M][5][5];
         Leading2D<M, EQ, double> G;
 #pragma unroll
         for (int n = 0; n <= 4; ++n) {
@@ -273,18 +312,25 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
                     if (a + n == 0) {
                         grp2d_leading<M, EQ>(JL, lo[0], P, as, G);
 #pragma unroll
-                        for (int c = 0; c < M; ++c) seed[c][0][0] = G.Ws[c];
+                        for (int c = 0; c < M; ++c) pseed[c][0][0] = park(G.Ws[c]);
                     } else {
                         double o[M];
                         grp2d_seed<M, EQ>(JL, lo[a], G, inv_fact[a] * inv_fact[n], o);
 #pragma unroll
-                        for (int c = 0; c < M; ++c) seed[c][a][n] = o[c];
+                        for (int c = 0; c < M; ++c) pseed[c][a][n] = park(o[c]);
                     }
                 }
             }
         }
         if (face) {
             double wt[M][5], Fg[M], Wg[M];
+            double seed[M][5][5];
+#pragma unroll
+            for (int c = 0; c < M; ++c)
+#pragma unroll
+                for (int a = 0; a < 5; ++a)
+#pragma unroll
+                    for (int b = 0; a + b < 5; ++b) seed[c][a][b] = unpark(pseed[c][a][b]);
             if constexpr (EQ == EULER) ck2d_euler(seed, P.gamma, wt);
             else ck2d_adv(seed[0], as, at, wt[0]);
             node_flux<M, EQ>(wt, dt, P, as, Fg, Wg);
