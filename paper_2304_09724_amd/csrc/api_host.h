@@ -63,7 +63,8 @@ constexpr int lines2d(int v) { return 1 << v; }
 // Device workspace carved out of the caller's buffer.
 struct Layout {
     size_t alt = 0, inst = 0, order = 0, queue = 0, ist = 0, t_end = 0, dt = 0,
-           flags = 0, tiles0 = 0, tiles1 = 0, parity = 0, last = 0, dt_fixed = 0,
+           flags = 0, tiles0 = 0, tiles1 = 0, act_inst = 0, act_off0 = 0, act_off1 = 0,
+           act_n = 0, parity = 0, last = 0, dt_fixed = 0,
            steps_left = 0, smax = 0, bad = 0, active = 0, gate = 0, faces = 0, trouble = 0,
            guard = 0, total = 0;
 };
@@ -88,6 +89,10 @@ inline Layout make_layout(const shw_mesh *meshes, int n_inst, const shw_params *
     L.flags = take(cells);
     L.tiles0 = take((size_t)N_TILE_VARIANTS * (n_inst + 1) * sizeof(int));
     L.tiles1 = take((size_t)N_TILE_VARIANTS * (n_inst + 1) * sizeof(int));
+    L.act_inst = take((size_t)n_inst * sizeof(int));
+    L.act_off0 = take((size_t)(n_inst + 1) * sizeof(int));
+    L.act_off1 = take((size_t)(n_inst + 1) * sizeof(int));
+    L.act_n = take(256);
     L.parity = take((size_t)n_inst * sizeof(int));
     L.last = take((size_t)n_inst * sizeof(int));
     L.dt_fixed = take((size_t)n_inst * sizeof(double));

@@ -70,6 +70,14 @@ struct Step2D {
     const Inst2D *inst;
     int n_inst;
     const int *tile_off[2];    // per sweep direction: first tile of each instance (n_inst+1)
+    // the running instances of the current step, rebuilt by compact2d_kernel
+    // after each step's step sizes are known: their ids in order (act_inst),
+    // per sweep direction the first tile of each in the running tiles'
+    // numbering (act_off[DIR], act_n + 1 entries), their number (act_n[0])
+    // and the running tiles per direction (act_n[1], act_n[2])
+    int *act_inst;
+    int *act_off[2];
+    int *act_n;
     double *state;             // caller's state buffer
     double *alt;               // ping-pong buffer
     int *parity;               // per instance: 1 = current state is in alt

@@ -315,6 +315,10 @@ static Step2D step2d_args(shw_ctx *c)
     S.n_inst = c->n_inst;
     S.tile_off[0] = c->at<int>(c->lay.tiles0) + (size_t)c->variant * (c->n_inst + 1);
     S.tile_off[1] = c->at<int>(c->lay.tiles1) + (size_t)c->variant * (c->n_inst + 1);
+    S.act_inst = c->at<int>(c->lay.act_inst);
+    S.act_off[0] = c->at<int>(c->lay.act_off0);
+    S.act_off[1] = c->at<int>(c->lay.act_off1);
+    S.act_n = c->at<int>(c->lay.act_n);
     S.state = c->state;
     S.alt = c->alt();
     S.parity = c->at<int>(c->lay.parity);

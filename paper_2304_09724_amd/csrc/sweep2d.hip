@@ -147,6 +147,16 @@ __device__ __forceinline__ int xcd_tile(int b, int nblocks)
     return x * q + min(x, r) + b / XCDS;
 }
 
+// The running tiles of a step (those of the instances still advancing,
+// numbered consecutively by compact2d_kernel) go to the grid's first
+// workgroups, dealt over the XCDs as above: as instances finish, the tiles
+// left still spread over all eight XCDs.  The grid is sized for every
+// instance's tiles; a workgroup past the running ones gets -1 and returns.
+__device__ __forceinline__ int xcd_running_tile(int b, int running)
+{
+    return b < running ? xcd_tile(b, running) : -1;
+}
+
 // Positivity safeguard records (Euler): record q of a face, q < 4 the flux
 // averaged over the step and the edge, 4 + 4g + c component c of the value at
 // t_{n+1} at edge node g; components in the (x, y) frame.  An instance's
@@ -169,16 +179,17 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
 {
     constexpr int NB = 64 * L;
     constexpr int M = NComp<EQ, 2>::M;
-    const int bid = xcd_tile(blockIdx.x, gridDim.x);
-    const int inst = find_instance(S.tile_off[DIR], S.n_inst, bid);
+    const int bid = xcd_running_tile(blockIdx.x, S.act_n[1 + DIR]);
+    if (bid < 0) return;
+    const int k = find_instance(S.act_off[DIR], S.act_n[0], bid);
+    const int inst = S.act_inst[k];
     const double dt = S.dt[inst];
-    if (!(dt > 0.0)) return;
     const Inst2D d = S.inst[inst];
     const int ns = DIR == 0 ? d.nx : d.ny, nt = DIR == 0 ? d.ny : d.nx;
     const double dS = DIR == 0 ? d.dx : d.dy, dT = DIR == 0 ? d.dy : d.dx;
     const double as = DIR == 0 ? P.adv_a : P.adv_b, at = DIR == 0 ? P.adv_b : P.adv_a;
     const int tiles_s = (ns + CHUNK - 1) / CHUNK, tiles_t = (nt + L - 1) / L;
-    const int tile = bid - S.tile_off[DIR][inst];
+    const int tile = bid - S.act_off[DIR][k];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     // consecutive tiles: along the lines for the x-sweep (a row band at a
     // time), across them for the y-sweep (a band of rows over all columns),
@@ -434,14 +445,15 @@ __global__ void __launch_bounds__(64 * L) gate2d_kernel(Step2D S, DevParams P)
 {
     constexpr int M = 4;
     __shared__ u32x4 s_gate[GATE_LDS_WORDS];
-    const int bid = xcd_tile(blockIdx.x, gridDim.x);
-    const int inst = find_instance(S.tile_off[0], S.n_inst, bid);
-    if (!(S.dt[inst] > 0.0)) return;              // the whole block: instance idle
+    const int bid = xcd_running_tile(blockIdx.x, S.act_n[1]);
+    if (bid < 0) return;                          // the whole block: no running tile
+    const int k = find_instance(S.act_off[0], S.act_n[0], bid);
+    const int inst = S.act_inst[k];
     gate_to_lds(S.gate, s_gate, threadIdx.x, 64 * L);
     __syncthreads();
     const Inst2D d = S.inst[inst];
     const int tiles_s = (d.nx + CHUNK - 1) / CHUNK;
-    const int tile = bid - S.tile_off[0][inst];
+    const int tile = bid - S.act_off[0][k];
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
     const int t = (tile / tiles_s) * L + wave;
     if (t >= d.ny) return;                        // the whole wave: past the last row
@@ -705,6 +717,59 @@ __global__ void prepare2d_kernel(Step2D S, DevParams P, int fixed)
     S.ist[i] = st;
 }
 
+// The running instances of this step (step size > 0) in order, and per sweep
+// direction the first tile of each in a consecutive numbering of their tiles
+// (one block: each thread counts a run of instances, a scan over the block
+// places the runs, each thread then writes its own).
+constexpr int COMPACT_THREADS = 1024;
+
+__global__ void __launch_bounds__(COMPACT_THREADS) compact2d_kernel(Step2D S)
+{
+    __shared__ int s_cnt[3][COMPACT_THREADS];
+    const int n = S.n_inst, tid = threadIdx.x;
+    const int per = (n + COMPACT_THREADS - 1) / COMPACT_THREADS;
+    const int i0 = min(tid * per, n), i1 = min(i0 + per, n);
+    int cnt = 0, tx = 0, ty = 0;
+    for (int i = i0; i < i1; ++i)
+        if (S.dt[i] > 0.0) {
+            ++cnt;
+            tx += S.tile_off[0][i + 1] - S.tile_off[0][i];
+            ty += S.tile_off[1][i + 1] - S.tile_off[1][i];
+        }
+    s_cnt[0][tid] = cnt;
+    s_cnt[1][tid] = tx;
+    s_cnt[2][tid] = ty;
+    __syncthreads();
+    // exclusive scan of the three counts over the block (Hillis-Steele on the
+    // inclusive sums, then shifted)
+    for (int o = 1; o < COMPACT_THREADS; o <<= 1) {
+        int v[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) v[q] = tid >= o ? s_cnt[q][tid - o] : 0;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 3; ++q) s_cnt[q][tid] += v[q];
+        __syncthreads();
+    }
+    int k = s_cnt[0][tid] - cnt, ox = s_cnt[1][tid] - tx, oy = s_cnt[2][tid] - ty;
+    for (int i = i0; i < i1; ++i)
+        if (S.dt[i] > 0.0) {
+            S.act_inst[k] = i;
+            S.act_off[0][k] = ox;
+            S.act_off[1][k] = oy;
+            ++k;
+            ox += S.tile_off[0][i + 1] - S.tile_off[0][i];
+            oy += S.tile_off[1][i + 1] - S.tile_off[1][i];
+        }
+    if (tid == COMPACT_THREADS - 1) {
+        S.act_off[0][k] = ox;
+        S.act_off[1][k] = oy;
+        S.act_n[0] = k;
+        S.act_n[1] = ox;
+        S.act_n[2] = oy;
+    }
+}
+
 // per instance, after a step: time, step count, parity, budget, activity
 __global__ void finish2d_kernel(Step2D S)
 {
@@ -778,6 +843,7 @@ hipError_t launch_step2d(int eq, const Step2D &S, const DevParams &P, int fixed,
 {
     const int nb = (S.n_inst + 255) / 256;
     prepare2d_kernel<<<nb, 256, 0, st>>>(S, P, fixed);
+    compact2d_kernel<<<1, COMPACT_THREADS, 0, st>>>(S);
     if (lines == 1) sweeps2d<1>(eq, S, P, total_tiles, st);
     else if (lines == 2) sweeps2d<2>(eq, S, P, total_tiles, st);
     else sweeps2d<4>(eq, S, P, total_tiles, st);

@@ -430,3 +430,29 @@ def test_autotuner_restores_nonphysical_flags():
         runs.append([s.get_state(i) for i in range(2)])
     for a, b in zip(*runs):
         assert np.array_equal(a, b)
+
+
+def test_ragged_batch_matches_instances_run_alone():
+    """Instances of a batch that finish at different times (own mesh sizes and
+    end times): each step's sweeps run only the tiles of the instances still
+    advancing, renumbered and spread over the XCDs.  Every instance's state
+    and step count equal those of the same instance advanced alone, bit for
+    bit, with graphs on."""
+    insts = WL.four_quadrant_batch(count=6, seed=23)
+    sizes = [64, 18, 130, 40, 96, 22]
+    ends = [0.02, 0.05, 0.01, 0.04, 0.03, 0.005]
+    meshes = [S.Mesh.rect(n, n, 0.0, 1.0, 0.0, 1.0, S.BC_TRANSMISSIVE, S.BC_TRANSMISSIVE)
+              for n in sizes]
+    states = [WL.four_quadrant(n, d.quads) for n, d in zip(sizes, insts)]
+    b = S.Solver(meshes, gparams())
+    for i, st in enumerate(states):
+        b.set_state(i, st)
+    steps = b.advance_to(np.array(ends), raise_nonphysical=False)
+    codes = b.instance_status()
+    assert len(set(steps.tolist())) > 3            # they do finish at different steps
+    for i, (m, st) in enumerate(zip(meshes, states)):
+        a = S.Solver([m], gparams())
+        a.set_state(0, st)
+        k = a.advance_to(ends[i], raise_nonphysical=False)
+        assert k[0] == steps[i] and a.instance_status()[0] == codes[i], i
+        assert np.array_equal(a.get_state(0), b.get_state(i)), i
