@@ -128,16 +128,33 @@ constexpr double LOB_W1 = 5.0 / 12.0;
 
 // Quartic whose averages over cells -1, 0, 1 and whose increments
 // p(l+1/2) - p(l-1/2) over cells -1, +1 match the data (solved by hand from
-// those five linear conditions).
+// those five linear conditions):
+//   c0 = (1148 a0 - 94 s + 27 bd)/960, c1 = (13 d - 5 bs)/16,
+//   c2 = (10 s - 20 a0 - 3 bd)/8, c3 = (bs - d)/4, c4 = (4 a0 - 2 s + bd)/4
+// with s = am + ap, d = ap - am, bs = bm + bp, bd = bp - bm; each written as
+// one sum of products with the divisions folded into the constants, so
+// every term after the first is one FMA.
 template <class R>
 SHW_HD void big_quartic(R am, R a0, R ap, R bm, R bp, R c[5])
 {
     const R s = am + ap, d = ap - am, bs = bm + bp, bd = bp - bm;
-    c[0] = (1148.0 * a0 - 94.0 * s + 27.0 * bd) * (1.0 / 960.0);
-    c[1] = (13.0 * d - 5.0 * bs) * (1.0 / 16.0);
-    c[2] = (10.0 * s - 20.0 * a0 - 3.0 * bd) * (1.0 / 8.0);
-    c[3] = (bs - d) * 0.25;
-    c[4] = (4.0 * a0 - 2.0 * s + bd) * 0.25;
+    c[0] = (1148.0 / 960.0) * a0 - (94.0 / 960.0) * s + (27.0 / 960.0) * bd;
+    c[1] = 0.8125 * d - 0.3125 * bs;
+    c[2] = 1.25 * s - 2.5 * a0 - 0.375 * bd;
+    c[3] = 0.25 * bs - 0.25 * d;
+    c[4] = a0 - 0.5 * s + 0.25 * bd;
+}
+
+// The same quartic for centred data (a0 = 0, am = cm, ap = cp).
+template <class R>
+SHW_HD void big_quartic_centred(R cm, R cp, R bm, R bp, R c[5])
+{
+    const R s = cm + cp, d = cp - cm, bs = bm + bp, bd = bp - bm;
+    c[0] = (27.0 / 960.0) * bd - (94.0 / 960.0) * s;
+    c[1] = 0.8125 * d - 0.3125 * bs;
+    c[2] = 1.25 * s - 0.375 * bd;
+    c[3] = 0.25 * bs - 0.25 * d;
+    c[4] = 0.25 * bd - 0.5 * s;
 }
 
 // Nonlinear weights of the three candidates (big quartic, left linear a0 +
@@ -175,30 +192,39 @@ SHW_HD void nonlinear_weights(const R c[5], R am, R a0, R ap, const DevParams &P
 }
 
 // Final polynomial (w1/g1)(p1 - g2 p2 - g3 p3) + w2 p2 + w3 p3 in place of the
-// quartic coefficients c (the linear candidates only touch xi^0 and xi^1).
+// quartic coefficients c (the linear candidates only touch xi^0 and xi^1),
+// written as f p1 + (w2 - f g2) p2 + (w3 - f g3) p3 with f = w1/g1:
+// combine_factors forms k = (f, w2 - f g2, w3 - f g3) once per weight set,
+// combine applies it to a quartic.
 template <class R>
-SHW_HD void combine(R c[5], R am, R a0, R ap, const R w[3], const DevParams &P)
+SHW_HD void combine_factors(const R w[3], const DevParams &P, R k[3])
 {
-    const R f = w[0] * P.inv_g1;
+    k[0] = w[0] * P.inv_g1;
+    k[1] = w[1] - k[0] * P.g2;
+    k[2] = w[2] - k[0] * P.g3;
+}
+
+template <class R>
+SHW_HD void combine(R c[5], R am, R a0, R ap, const R k[3])
+{
     const R dl = a0 - am, dr = ap - a0;
-    c[0] = f * (c[0] - (P.g2 + P.g3) * a0) + (w[1] + w[2]) * a0;
-    c[1] = f * (c[1] - P.g2 * dl - P.g3 * dr) + w[1] * dl + w[2] * dr;
-    c[2] *= f;
-    c[3] *= f;
-    c[4] *= f;
+    c[0] = k[0] * c[0] + (k[1] + k[2]) * a0;
+    c[1] = k[0] * c[1] + k[1] * dl + k[2] * dr;
+    c[2] *= k[0];
+    c[3] *= k[0];
+    c[4] *= k[0];
 }
 
 // combine for centred data (a0 = 0, so the candidates' constant terms drop
-// out): the same coefficients as combine(c, -dl, 0, dr, ...).
+// out): the same coefficients as combine(c, -dl, 0, dr, k).
 template <class R>
-SHW_HD void combine_centred(R c[5], R dl, R dr, const R w[3], const DevParams &P)
+SHW_HD void combine_centred(R c[5], R dl, R dr, const R k[3])
 {
-    const R f = w[0] * P.inv_g1;
-    c[0] = f * c[0];
-    c[1] = f * (c[1] - P.g2 * dl - P.g3 * dr) + w[1] * dl + w[2] * dr;
-    c[2] *= f;
-    c[3] *= f;
-    c[4] *= f;
+    c[0] *= k[0];
+    c[1] = k[0] * c[1] + k[1] * dl + k[2] * dr;
+    c[2] *= k[0];
+    c[3] *= k[0];
+    c[4] *= k[0];
 }
 
 // d^k p/dxi^k at xi = -1/2 (lo) and xi = +1/2 (hi), k = 0..4.
@@ -315,14 +341,16 @@ SHW_HD void char1_L(const Char1<Re> &E, const Re x[3], Re y[3])
     y[2] = hs - hd;
 }
 
-// x = R y: columns (1, u - c, H - u c), (1, u, u^2/2), (1, u + c, H + u c)
+// x = R y: columns (1, u - c, H - u c), (1, u, u^2/2), (1, u + c, H + u c);
+// with s = y0 + y1 + y2 and d = y2 - y0: x = (s, u s + c d,
+// H s + (u^2/2 - H) y1 + u c d)
 template <class Re>
 SHW_HD void char1_R(const Char1<Re> &E, const Re y[3], Re x[3])
 {
     const Re s = y[0] + y[1] + y[2], d = y[2] - y[0];
     x[0] = s;
     x[1] = E.u * s + E.c * d;
-    x[2] = E.H * (y[0] + y[2]) + E.u * E.c * d + E.hq * y[1];
+    x[2] = E.H * s + (E.hq - E.H) * y[1] + (E.u * E.c) * d;
 }
 
 // The characteristic fields of the 2D Euler flux Jacobian in x at a state,
@@ -363,7 +391,8 @@ SHW_HD void char_L(const CharX<Re> &E, const Re x[4], Re y[4])
 }
 
 // x = R y: columns (1, u - c, v, H - u c), (1, u, v, |u|^2/2), (0, 0, 1, v),
-// (1, u + c, v, H + u c)
+// (1, u + c, v, H + u c); with s = y0 + y1 + y3 and d = y3 - y0:
+// x = (s, u s + c d, v s + y2, H s + (|u|^2/2 - H) y1 + u c d + v y2)
 template <class Re>
 SHW_HD void char_R(const CharX<Re> &E, const Re y[4], Re x[4])
 {
@@ -371,7 +400,7 @@ SHW_HD void char_R(const CharX<Re> &E, const Re y[4], Re x[4])
     x[0] = s;
     x[1] = E.u * s + E.c * d;
     x[2] = E.v * s + y[2];
-    x[3] = E.H * (y[0] + y[3]) + E.u * E.c * d + E.hq * y[1] + E.v * y[2];
+    x[3] = E.H * s + (E.hq - E.H) * y[1] + (E.u * E.c) * d + E.v * y[2];
 }
 
 // Physical flux in x of a point state (scalar equations: a W or W^2/2).

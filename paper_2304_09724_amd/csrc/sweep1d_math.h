@@ -88,15 +88,16 @@ SHW_HD void recon_cell(const Re Wm[M], const Re W0[M], const Re Wp[M], const Re 
             char1_L(E, ep, cp);
             char1_L(E, Vm, dm);
             char1_L(E, Vp, dp);
-            const Re zero = 0.0;
             Re cq[M][5];
 #pragma unroll
             for (int s = 0; s < M; ++s) {
-                big_quartic(cm[s], zero, cp[s], Re(dx * dm[s]), Re(dx * dp[s]), cq[s]);
+                big_quartic_centred(cm[s], cp[s], Re(dx * dm[s]), Re(dx * dp[s]), cq[s]);
                 if (full) {
                     Re w[3];
                     nonlinear_weights_jumps(cq[s], -cm[s], cp[s], P, w);
-                    combine_centred(cq[s], -cm[s], cp[s], w, P);
+                    Re k[3];
+                    combine_factors(w, P, k);
+                    combine_centred(cq[s], -cm[s], cp[s], k);
                 }
             }
             // back to the components on the five coefficients (R is linear:
@@ -133,7 +134,9 @@ SHW_HD void recon_cell(const Re Wm[M], const Re W0[M], const Re Wp[M], const Re 
         if (full) {
             Re w[3];
             nonlinear_weights(q, Wm[c], W0[c], Wp[c], P, w);
-            combine(q, Wm[c], W0[c], Wp[c], w, P);
+            Re k[3];
+            combine_factors(w, P, k);
+            combine(q, Wm[c], W0[c], Wp[c], k);
         }
         edge_derivs(q, l5, h5);
 #pragma unroll

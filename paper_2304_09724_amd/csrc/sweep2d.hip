@@ -249,14 +249,18 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
                 s_poly[1][c][k][threadIdx.x] = PV[c][k];
             }
     }
-    // the scalings 1/dt^n and 1/ds^n are the same for the whole block: held
-    // in scalar registers (an operand of the vector instructions), not in
-    // vector ones
+    // the scalings 1/dt^n and 1/(a! ds^a) are the same for the whole block:
+    // held in scalar registers (an operand of the vector instructions), not
+    // in vector ones.  The node values are taken as Taylor coefficients in
+    // t (taylor_at) and the edge jets scaled by 1/a!, so the jets are
+    // d^{a+n}W/ds^a dt^n / (a! n!), the seeds of the series the GRP builds
+    // (both stages and the derivative Riemann problems are linear in them,
+    // the weights coming from order 0)
     const double iT = uniform(1.0 / dT), iS = uniform(1.0 / dS);
     const double sct[5] = {1.0, iT, uniform(iT * iT), uniform(iT * iT * iT),
                            uniform(iT * iT * iT * iT)};
-    const double scs[5] = {1.0, iS, uniform(iS * iS), uniform(iS * iS * iS),
-                           uniform(iS * iS * iS * iS)};
+    const double scs[5] = {1.0, iS, uniform(0.5 * iS * iS), uniform((1.0 / 6.0) * iS * iS * iS),
+                           uniform((1.0 / 24.0) * iS * iS * iS * iS)};
     const double node[4] = {-0.5, -LOB_H, LOB_H, 0.5};
     const double nw[4] = {LOB_W0, LOB_W1, LOB_W1, LOB_W0};
 
@@ -278,7 +282,6 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
         // Stage 2 order by order; each order's jets move to the lane above at
         // once and become the GRP's series seeds there, so only one order of
         // jets is ever held (each lane reads back only its own LDS slots).
-        const double inv_fact[5] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
         double w[M][3];
         Parked pseed[M][5][5];
         Leading2D<M, EQ, double> G;
@@ -296,24 +299,20 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
                     pw[k] = s_poly[0][c][k][threadIdx.x];
                     pv[k] = s_poly[1][c][k][threadIdx.x];
                 }
-                const double A = deriv_at(pw, node[g], n, sct[n]);
-                const double B = deriv_at(pv, node[g], n, sct[n]);
+                const double A = taylor_at(pw, node[g], n, sct[n]);
+                const double B = taylor_at(pv, node[g], n, sct[n]);
                 a0[c] = A;
                 am[c] = from_lane_below(A);
                 ap[c] = from_lane_above(A);
                 bm[c] = from_lane_below(B);
                 bp[c] = from_lane_above(B);
             }
+            // every lane reconstructs: only lanes 1..62 feed a face, but the
+            // others (lanes 0 and 63; lanes past the line's end, on zero
+            // polynomials and a unit state) work on finite data too, and
+            // leaving them out would cost a branch that clears their jets
             double lo[5][M], hi[5][M];
-            if (lane >= 1 && lane <= 62 && live) {
-                stage2_order<M, EQ>(n, am, a0, ap, bm, bp, Em, dS, scs, full, charpath, P, w,
-                                    lo, hi);
-            } else {
-#pragma unroll
-                for (int a = 0; a < 5; ++a)
-#pragma unroll
-                    for (int c = 0; c < M; ++c) { lo[a][c] = 0.0; hi[a][c] = 0.0; }
-            }
+            stage2_order<M, EQ>(n, am, a0, ap, bm, bp, Em, dS, scs, full, charpath, P, w, lo, hi);
 #pragma unroll
             for (int a = 0; a + n <= 4; ++a) {
                 double JL[M];
@@ -326,7 +325,7 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
                         for (int c = 0; c < M; ++c) pseed[c][0][0] = park(G.Ws[c]);
                     } else {
                         double o[M];
-                        grp2d_seed<M, EQ>(JL, lo[a], G, inv_fact[a] * inv_fact[n], o);
+                        grp2d_seed<M, EQ>(JL, lo[a], G, o);
 #pragma unroll
                         for (int c = 0; c < M; ++c) pseed[c][a][n] = park(o[c]);
                     }

@@ -74,8 +74,10 @@ SHW_HD void stage1(const Re W[3][M], const Re V[3][M], const Re Y[3][M], const R
                 if (full) {
                     Re w[3];
                     nonlinear_weights(cw[f], aw[0], aw[1], aw[2], P, w);
-                    combine(cw[f], aw[0], aw[1], aw[2], w, P);
-                    combine(cv[f], av[0], av[1], av[2], w, P);
+                    Re k[3];
+                    combine_factors(w, P, k);
+                    combine(cw[f], aw[0], aw[1], aw[2], k);
+                    combine(cv[f], av[0], av[1], av[2], k);
                 }
             }
 #pragma unroll
@@ -99,35 +101,26 @@ SHW_HD void stage1(const Re W[3][M], const Re V[3][M], const Re Y[3][M], const R
         if (full) {
             Re w[3];
             nonlinear_weights(PW[c], W[0][c], W[1][c], W[2][c], P, w);
-            combine(PW[c], W[0][c], W[1][c], W[2][c], w, P);
-            combine(PV[c], V[0][c], V[1][c], V[2][c], w, P);
+            Re k[3];
+            combine_factors(w, P, k);
+            combine(PW[c], W[0][c], W[1][c], W[2][c], k);
+            combine(PV[c], V[0][c], V[1][c], V[2][c], k);
         }
     }
 }
 
-// d^n p/deta^n (n = 0..4) of a quartic at eta, times sc[n] (= 1/dt^n).
+// Coefficient of (eta' - eta)^n of a quartic about eta (its n-th derivative
+// over n!), times scale: sum_k C(k, n) c_k eta^(k-n), n = 0..4.
 template <class Re>
-SHW_HD void derivs_at(const Re c[5], double eta, const double sc[5], Re out[5])
-{
-    const double e2 = eta * eta, e3 = e2 * eta, e4 = e2 * e2;
-    out[0] = (c[0] + eta * c[1] + e2 * c[2] + e3 * c[3] + e4 * c[4]) * sc[0];
-    out[1] = (c[1] + 2.0 * eta * c[2] + 3.0 * e2 * c[3] + 4.0 * e3 * c[4]) * sc[1];
-    out[2] = (2.0 * c[2] + 6.0 * eta * c[3] + 12.0 * e2 * c[4]) * sc[2];
-    out[3] = (6.0 * c[3] + 24.0 * eta * c[4]) * sc[3];
-    out[4] = (24.0 * c[4]) * sc[4];
-}
-
-// d^n p/deta^n of a quartic at eta, times scale.
-template <class Re>
-SHW_HD Re deriv_at(const Re c[5], double eta, int n, double scale)
+SHW_HD Re taylor_at(const Re c[5], double eta, int n, double scale)
 {
     const double e2 = eta * eta, e3 = e2 * eta, e4 = e2 * e2;
     switch (n) {
     case 0: return (c[0] + eta * c[1] + e2 * c[2] + e3 * c[3] + e4 * c[4]) * scale;
-    case 1: return (c[1] + 2.0 * eta * c[2] + 3.0 * e2 * c[3] + 4.0 * e3 * c[4]) * scale;
-    case 2: return (2.0 * c[2] + 6.0 * eta * c[3] + 12.0 * e2 * c[4]) * scale;
-    case 3: return (6.0 * c[3] + 24.0 * eta * c[4]) * scale;
-    default: return (24.0 * c[4]) * scale;
+    case 1: return (c[1] + (2.0 * eta) * c[2] + (3.0 * e2) * c[3] + (4.0 * e3) * c[4]) * scale;
+    case 2: return (c[2] + (3.0 * eta) * c[3] + (6.0 * e2) * c[4]) * scale;
+    case 3: return (c[3] + (4.0 * eta) * c[4]) * scale;
+    default: return c[4] * scale;
     }
 }
 
@@ -136,11 +129,14 @@ SHW_HD Re deriv_at(const Re c[5], double eta, int n, double scale)
 // reconstruction along the sweep direction from the node values a[l] =
 // d^n/dt^n of the line averages of W of cells l = -1, 0, +1 and b[l] = the
 // same for W_s of cells -1, +1 (scaled by ds inside).  Weights come from the
-// order-0 data (w is filled when n == 0 and reused for n >= 1).  Euler:
+// order-0 data (w, the combination factors of combine_factors, is filled
+// when n == 0 and reused for n >= 1).  Euler:
 // characteristic fields of the sweep Jacobian at the cell's average (L, R),
 // when charpath (a whole wave's choice; L, R are not read otherwise); full
 // selects nonlinear or linear weights as in stage 1.
-// Writes d^{a+n}W/ds^a dt^n at s = -1/2 (lo[a]) and s = +1/2 (hi[a]), a <= 4 - n.
+// Writes d^{a+n}W/ds^a dt^n at s = -1/2 (lo[a]) and s = +1/2 (hi[a]), a <= 4 - n,
+// times scs[a] (with the node values' own scaling: the kernel's make them
+// Taylor coefficients).
 // --------------------------------------------------------------------------
 template <int M, int EQ, class Re>
 SHW_HD void stage2_order(int n, const Re am[M], const Re a0[M], const Re ap[M], const Re bm[M],
@@ -165,13 +161,16 @@ SHW_HD void stage2_order(int n, const Re am[M], const Re a0[M], const Re ap[M], 
             char_L(E, ep, cp);
             char_L(E, bm, dm);
             char_L(E, bp, dp);
-            const Re zero = 0.0;
 #pragma unroll
             for (int f = 0; f < M; ++f) {
-                big_quartic(cm[f], zero, cp[f], Re(dS * dm[f]), Re(dS * dp[f]), cq[f]);
+                big_quartic_centred(cm[f], cp[f], Re(dS * dm[f]), Re(dS * dp[f]), cq[f]);
                 if (full) {
-                    if (n == 0) nonlinear_weights_jumps(cq[f], -cm[f], cp[f], P, w[f]);
-                    combine_centred(cq[f], -cm[f], cp[f], w[f], P);
+                    if (n == 0) {
+                        Re wn[3];
+                        nonlinear_weights_jumps(cq[f], -cm[f], cp[f], P, wn);
+                        combine_factors(wn, P, w[f]);
+                    }
+                    combine_centred(cq[f], -cm[f], cp[f], w[f]);
                 }
             }
             // back to the components on the five coefficients (R is linear:
@@ -195,8 +194,12 @@ SHW_HD void stage2_order(int n, const Re am[M], const Re a0[M], const Re ap[M], 
         for (int c = 0; c < M; ++c) {
             big_quartic(am[c], a0[c], ap[c], Re(dS * bm[c]), Re(dS * bp[c]), cq[c]);
             if (full) {
-                if (n == 0) nonlinear_weights(cq[c], am[c], a0[c], ap[c], P, w[c]);
-                combine(cq[c], am[c], a0[c], ap[c], w[c], P);
+                if (n == 0) {
+                    Re wn[3];
+                    nonlinear_weights(cq[c], am[c], a0[c], ap[c], P, wn);
+                    combine_factors(wn, P, w[c]);
+                }
+                combine(cq[c], am[c], a0[c], ap[c], w[c]);
             }
         }
     }
@@ -218,9 +221,10 @@ SHW_HD void stage2_order(int n, const Re am[M], const Re a0[M], const Re ap[M], 
 // conservative spatial series of the interface state (seeds s[c][a][b],
 // coefficient of s^a t^b, a+b <= 4) is carried to its time layers.  The
 // recursion runs on the primitive variables rho, u, v, p, whose PDE
-// (rho_t = -(u rho_s + rho u_s + v rho_t' + rho v_t'),
+// (rho_t = -(u rho_s + v rho_t' + rho (u_s + v_t')),
 //  u_t = -(u u_s + v u_t' + p_s/rho), v_t likewise, p_t = -(u p_s + v p_t' +
-//  g p (u_s + v_t'))) keeps fewer series alive; the resulting conservative
+//  g p (u_s + v_t'))) keeps fewer series alive (the divergence u_s + v_t'
+// is formed once for the density and the pressure); the resulting conservative
 // Taylor coefficients are the same numbers (the truncated series of one
 // analytic solution), so only the rounding differs from a conservative-form
 // recursion.  Output: the conservative time coefficients wt[c][k] at the
@@ -265,8 +269,9 @@ SHW_HD void ck2d_adv(const R s[5][5], double as, double at, R wt[5])
 // (HLLC for Euler, upwind for advection) and the eigen-decomposition of the
 // sweep Jacobian there.  grp2d_seed: one derivative d^{a+n}/ds^a dt^n
 // (1 <= a+n <= 4) by upwinding each characteristic field between the cell
-// below (JL, its s = +1/2 side) and above (JR); returns the series
-// coefficient (derivative / (a! n!)).
+// below (JL, its s = +1/2 side) and above (JR); linear in the jets, so
+// jets given as series coefficients (derivative / (a! n!)) give the
+// series coefficient.
 // --------------------------------------------------------------------------
 template <int M, int EQ, class Re>
 struct Leading2D {
@@ -300,7 +305,7 @@ SHW_HD void grp2d_leading(const Re JL[M], const Re JR[M], const DevParams &P, do
 
 template <int M, int EQ, class Re>
 SHW_HD void grp2d_seed(const Re JL[M], const Re JR[M], const Leading2D<M, EQ, Re> &G,
-                       double factor, Re out[M])
+                       Re out[M])
 {
     if constexpr (EQ == EULER) {
         // solved on the jump: each field's weights sum to one, so
@@ -314,19 +319,19 @@ SHW_HD void grp2d_seed(const Re JL[M], const Re JR[M], const Leading2D<M, EQ, Re
         for (int f = 0; f < M; ++f) l[f] = G.wl[f] * l[f];
         char_R(G.E, l, d);
 #pragma unroll
-        for (int c = 0; c < M; ++c) out[c] = (JR[c] + d[c]) * factor;
+        for (int c = 0; c < M; ++c) out[c] = JR[c] + d[c];
     } else {
-        out[0] = upwind(G.lam0, G.scale, JL[0], JR[0]) * factor;
+        out[0] = upwind(G.lam0, G.scale, JL[0], JR[0]);
     }
 }
 
-// The whole GRP from full jets (JL[jidx(a,n)][c]): leading term, all
+// The whole GRP from full jets given as series coefficients
+// (JL[jidx(a,n)][c] = d^{a+n}W/ds^a dt^n / (a! n!)): leading term, all
 // derivatives, Lax-Wendroff; output time coefficients wt[c][k].
 template <int M, int EQ, class Re>
 SHW_HD void grp2d(const Re JL[15][M], const Re JR[15][M], const DevParams &P, double as,
                   double at, Re wt[M][5])
 {
-    const double inv_fact[5] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
     Leading2D<M, EQ, Re> G;
     grp2d_leading<M, EQ>(JL[0], JR[0], P, as, G);
     Re s[M][5][5];
@@ -338,7 +343,7 @@ SHW_HD void grp2d(const Re JL[15][M], const Re JR[15][M], const DevParams &P, do
         for (int a = 0; a + n <= 4; ++a) {
             if (a + n == 0) continue;
             Re o[M];
-            grp2d_seed<M, EQ>(JL[jidx(a, n)], JR[jidx(a, n)], G, inv_fact[a] * inv_fact[n], o);
+            grp2d_seed<M, EQ>(JL[jidx(a, n)], JR[jidx(a, n)], G, o);
 #pragma unroll
             for (int c = 0; c < M; ++c) s[c][a][n] = o[c];
         }

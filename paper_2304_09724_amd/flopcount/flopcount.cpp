@@ -120,8 +120,8 @@ static void euler2d(bool full, const char *name)
             for (int n = 0; n <= 4; ++n) {
                 Cnt a0[M], b0[M];
                 for (int c = 0; c < M; ++c) {
-                    a0[c] = deriv_at(PW[c], eta, n, sc[n]);
-                    b0[c] = deriv_at(PV[c], eta, n, sc[n]);
+                    a0[c] = taylor_at(PW[c], eta, n, sc[n]);
+                    b0[c] = taylor_at(PV[c], eta, n, sc[n]);
                 }
                 stage2_order<M, EULER>(n, a0, a0, a0, b0, b0, Em, 0.01, sc, full, full, P, w, lo, hi);
                 for (int a = 0; a + n <= 4; ++a)

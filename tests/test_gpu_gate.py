@@ -416,10 +416,13 @@ def test_trained_gate_keeps_the_2d_solution(trained, case):
 def test_gate_speeds_up_2d_runs(trained):
     """The point of the gate: on a 2D problem with shocks and smooth regions
     (four-quadrant, 512^2, 20 steps) the learned gate runs faster than the
-    plain scheme by at least 5%, best of three each (1.08x measured; 1.12x
-    before the plain path's stage 2 moved to coefficient-space projections,
-    1.25x before its characteristic fields went to closed form: each shrank
-    the share of the work the gate saves)."""
+    plain scheme, by at least 2%, best of three each (1.04x measured once the
+    combination of the candidate polynomials took one factor set per weight
+    set; 1.08x before that, 1.12x before the plain path's stage 2 moved to
+    coefficient-space projections, 1.25x before its characteristic fields
+    went to closed form: each made the nonlinear path cheaper and shrank the
+    share of the work the gate saves).  The 256-problem batch of the
+    benchmark gains 1.06x."""
     import time
     params = trained[2]
     n = 512
@@ -447,4 +450,4 @@ def test_gate_speeds_up_2d_runs(trained):
     t_plain = best(S.Params.make(eq=S.EULER))
     t_gated = best(S.Params.make(eq=S.EULER, weights=S.W_LEARNED, gate_threshold=0.05))
     print(f"four-quadrant 512^2, 20 steps: gated {t_plain / t_gated:.3f}x plain")
-    assert t_plain / t_gated >= 1.05, (t_plain, t_gated)
+    assert t_plain / t_gated >= 1.02, (t_plain, t_gated)
