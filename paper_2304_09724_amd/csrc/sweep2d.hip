@@ -174,7 +174,9 @@ __device__ __forceinline__ long long yface_rec(const Inst2D &d, int q, int i, in
     return d.face_off + (long long)REC * d.ny * (d.nx + 1) + ((long long)q * (d.ny + 1) + f) * d.nx + i;
 }
 
-template <int EQ, int DIR, int L>
+// FULL: every cell takes the nonlinear weights (the paper's scheme): the
+// per-cell choice and its branches compile away.
+template <int EQ, int DIR, int L, bool FULL>
 __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
 {
     constexpr int NB = 64 * L;
@@ -211,7 +213,7 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
     // is free; the layout [coefficient][lane] keeps accesses conflict-free.
     __shared__ double s_poly[2][M][5][NB];
     double Wc[M];
-    bool full = P.weights == W_NONLINEAR;
+    bool full = FULL || P.weights == W_NONLINEAR;
     bool charpath;
     {
         double PW[M][5], PV[M][5];
@@ -223,11 +225,12 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
                 const long long ol = load_cell2d<EQ, M, DIR>(src, d, s, t - 1 + l, W[l], V[l], Y[l], Z[l]);
                 if (l == 1) o = ol;
             }
-            if (P.weights == W_GATED || P.weights == W_LEARNED) full = S.flags[d.cell_off + o] != 0;
+            if constexpr (!FULL)
+                if (P.weights == W_GATED || P.weights == W_LEARNED) full = S.flags[d.cell_off + o] != 0;
         }
         // one reconstruction path per wave: characteristic if any lane needs
         // the nonlinear weights
-        charpath = __any(full);
+        charpath = FULL || __any(full);
         if (live) {
             stage1<M, EQ>(W, V, Y, Z, dT, full, charpath, P, PW, PV);
 #pragma unroll
@@ -828,12 +831,15 @@ static void sweeps2d(int eq, const Step2D &S, const DevParams &P, const int tota
 {
     if (eq == EULER && P.weights == W_LEARNED)
         gate2d_kernel<L><<<total_tiles[0], 64 * L, 0, st>>>(S, P);
-    if (eq == EULER) {
-        sweep2d_kernel<EULER, 0, L><<<total_tiles[0], 64 * L, 0, st>>>(S, P);
-        sweep2d_kernel<EULER, 1, L><<<total_tiles[1], 64 * L, 0, st>>>(S, P);
+    if (eq == EULER && P.weights == W_NONLINEAR) {
+        sweep2d_kernel<EULER, 0, L, true><<<total_tiles[0], 64 * L, 0, st>>>(S, P);
+        sweep2d_kernel<EULER, 1, L, true><<<total_tiles[1], 64 * L, 0, st>>>(S, P);
+    } else if (eq == EULER) {
+        sweep2d_kernel<EULER, 0, L, false><<<total_tiles[0], 64 * L, 0, st>>>(S, P);
+        sweep2d_kernel<EULER, 1, L, false><<<total_tiles[1], 64 * L, 0, st>>>(S, P);
     } else {
-        sweep2d_kernel<ADV, 0, L><<<total_tiles[0], 64 * L, 0, st>>>(S, P);
-        sweep2d_kernel<ADV, 1, L><<<total_tiles[1], 64 * L, 0, st>>>(S, P);
+        sweep2d_kernel<ADV, 0, L, false><<<total_tiles[0], 64 * L, 0, st>>>(S, P);
+        sweep2d_kernel<ADV, 1, L, false><<<total_tiles[1], 64 * L, 0, st>>>(S, P);
     }
 }
 

@@ -71,14 +71,16 @@ SHW_HD void stage1(const Re W[3][M], const Re V[3][M], const Re Y[3][M], const R
                 const Re bv[2] = {dT * pz[0][f], dT * pz[1][f]};
                 big_quartic(aw[0], aw[1], aw[2], bw[0], bw[1], cw[f]);
                 big_quartic(av[0], av[1], av[2], bv[0], bv[1], cv[f]);
-                if (full) {
-                    Re w[3];
-                    nonlinear_weights(cw[f], aw[0], aw[1], aw[2], P, w);
-                    Re k[3];
-                    combine_factors(w, P, k);
-                    combine(cw[f], aw[0], aw[1], aw[2], k);
-                    combine(cv[f], av[0], av[1], av[2], k);
-                }
+                // every lane of a characteristic wave combines (no divergent
+                // branch); a linear-weight cell takes the factors (1, 0, 0),
+                // which leave the big quartic as it is
+                Re w[3];
+                nonlinear_weights(cw[f], aw[0], aw[1], aw[2], P, w);
+                Re k[3];
+                combine_factors(w, P, k);
+                if (!full) { k[0] = 1.0; k[1] = 0.0; k[2] = 0.0; }
+                combine(cw[f], aw[0], aw[1], aw[2], k);
+                combine(cv[f], av[0], av[1], av[2], k);
             }
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
@@ -164,14 +166,15 @@ SHW_HD void stage2_order(int n, const Re am[M], const Re a0[M], const Re ap[M], 
 #pragma unroll
             for (int f = 0; f < M; ++f) {
                 big_quartic_centred(cm[f], cp[f], Re(dS * dm[f]), Re(dS * dp[f]), cq[f]);
-                if (full) {
-                    if (n == 0) {
-                        Re wn[3];
-                        nonlinear_weights_jumps(cq[f], -cm[f], cp[f], P, wn);
-                        combine_factors(wn, P, w[f]);
-                    }
-                    combine_centred(cq[f], -cm[f], cp[f], w[f]);
+                // as in stage 1: every lane combines, a linear-weight cell
+                // with the factors (1, 0, 0)
+                if (n == 0) {
+                    Re wn[3];
+                    nonlinear_weights_jumps(cq[f], -cm[f], cp[f], P, wn);
+                    combine_factors(wn, P, w[f]);
+                    if (!full) { w[f][0] = 1.0; w[f][1] = 0.0; w[f][2] = 0.0; }
                 }
+                combine_centred(cq[f], -cm[f], cp[f], w[f]);
             }
             // back to the components on the five coefficients (R is linear:
             // the same polynomials as mapping the 2 (5 - n) edge jets)
