@@ -442,49 +442,66 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
 // score reaches the threshold.  Both sweeps of the step read the flags.
 // Tiles as for the x-sweep: L rows x 60 cells, one wave per row, lane l on
 // cell c0 + l - 2 (every lane evaluates; lanes 2..61 store).
+// A lane's slice of the packed network (256 bytes) read straight from
+// global memory: the 16 KB network stays in the caches, and each wave of the
+// gate kernel reads it once for all its tiles.
+__device__ __forceinline__ GateLane gate_lane_global(const GateLane *g, int lane)
+{
+    GateLane G;
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(g + lane);
+    u32x4 *dst = reinterpret_cast<u32x4 *>(&G);
+#pragma unroll
+    for (int w = 0; w < 16; ++w) dst[w] = src[w];
+    return G;
+}
+
 template <int L>
 __global__ void __launch_bounds__(64 * L) gate2d_kernel(Step2D S, DevParams P)
 {
     constexpr int M = 4;
-    __shared__ u32x4 s_gate[GATE_LDS_WORDS];
-    const int bid = xcd_running_tile(blockIdx.x, S.act_n[1]);
-    if (bid < 0) return;                          // the whole block: no running tile
-    const int k = find_instance(S.act_off[0], S.act_n[0], bid);
-    const int inst = S.act_inst[k];
-    gate_to_lds(S.gate, s_gate, threadIdx.x, 64 * L);
-    __syncthreads();
-    const Inst2D d = S.inst[inst];
-    const int tiles_s = (d.nx + CHUNK - 1) / CHUNK;
-    const int tile = bid - S.act_off[0][k];
+    // The grid holds as many workgroups as the device runs at once (a
+    // multiple of 8); each walks the running tiles with the grid's stride
+    // (tile numbers v = blockIdx.x + k gridDim.x stay on this workgroup's
+    // XCD, v mod 8), with the network in registers throughout.  No LDS, so
+    // the registers alone bound the waves per SIMD.
     const int lane = threadIdx.x % WAVE, wave = threadIdx.x / WAVE;
-    const int t = (tile / tiles_s) * L + wave;
-    if (t >= d.ny) return;                        // the whole wave: past the last row
-    const int s = (tile % tiles_s) * CHUNK + lane - 2;
-    const int sc = s < 0 ? 0 : (s >= d.nx ? d.nx - 1 : s);   // lanes off the row: any cell
-    const double *src = (S.parity[inst] ? S.alt : S.state) + d.off;
-    const GateLane G = gate_lane_lds(s_gate, lane);
-    float z[2];
-    {
-        double Wm[M], W0[M], Wp[M], Vm[M], V0[M], Vp[M], Y[M], Z[M];
-        load_cell2d<EULER, M, 0>(src, d, sc - 1, t, Wm, Vm, Y, Z);
-        load_cell2d<EULER, M, 0>(src, d, sc, t, W0, V0, Y, Z);
-        load_cell2d<EULER, M, 0>(src, d, sc + 1, t, Wp, Vp, Y, Z);
-        float f[GATE_NF];
-        gate_features<M>(Wm, W0, Wp, Vm, Vp, d.dx, P.gamma, f);
-        z[0] = gate_wave_logit(f, G);
+    const GateLane G = gate_lane_global(S.gate, lane);
+    const int running = S.act_n[1];
+    for (int v = blockIdx.x; v < running; v += gridDim.x) {
+        const int bid = xcd_tile(v, running);
+        const int k = find_instance(S.act_off[0], S.act_n[0], bid);
+        const int inst = S.act_inst[k];
+        const Inst2D d = S.inst[inst];
+        const int tiles_s = (d.nx + CHUNK - 1) / CHUNK;
+        const int tile = bid - S.act_off[0][k];
+        const int t = (tile / tiles_s) * L + wave;
+        if (t >= d.ny) continue;                  // the whole wave: past the last row
+        const int s = (tile % tiles_s) * CHUNK + lane - 2;
+        const int sc = s < 0 ? 0 : (s >= d.nx ? d.nx - 1 : s);   // lanes off the row: any cell
+        const double *src = (S.parity[inst] ? S.alt : S.state) + d.off;
+        float z[2];
+        {
+            double Wm[M], W0[M], Wp[M], Vm[M], V0[M], Vp[M], Y[M], Z[M];
+            load_cell2d<EULER, M, 0>(src, d, sc - 1, t, Wm, Vm, Y, Z);
+            load_cell2d<EULER, M, 0>(src, d, sc, t, W0, V0, Y, Z);
+            load_cell2d<EULER, M, 0>(src, d, sc + 1, t, Wp, Vp, Y, Z);
+            float f[GATE_NF];
+            gate_features<M>(Wm, W0, Wp, Vm, Vp, d.dx, P.gamma, f);
+            z[0] = gate_wave_logit(f, G);
+        }
+        {
+            double Wm[M], W0[M], Wp[M], Vm[M], V0[M], Vp[M], Y[M], Z[M];
+            load_cell2d<EULER, M, 1>(src, d, t - 1, sc, Wm, Vm, Y, Z);
+            load_cell2d<EULER, M, 1>(src, d, t, sc, W0, V0, Y, Z);
+            load_cell2d<EULER, M, 1>(src, d, t + 1, sc, Wp, Vp, Y, Z);
+            float f[GATE_NF];
+            gate_features<M>(Wm, W0, Wp, Vm, Vp, d.dy, P.gamma, f);
+            z[1] = gate_wave_logit(f, G);
+        }
+        if (lane >= 2 && lane <= 61 && s < d.nx)
+            S.flags[d.cell_off + (long long)t * d.nx + s] =
+                (uint8_t)(fmaxf(z[0], z[1]) >= S.gate_logit_min);
     }
-    {
-        double Wm[M], W0[M], Wp[M], Vm[M], V0[M], Vp[M], Y[M], Z[M];
-        load_cell2d<EULER, M, 1>(src, d, t - 1, sc, Wm, Vm, Y, Z);
-        load_cell2d<EULER, M, 1>(src, d, t, sc, W0, V0, Y, Z);
-        load_cell2d<EULER, M, 1>(src, d, t + 1, sc, Wp, Vp, Y, Z);
-        float f[GATE_NF];
-        gate_features<M>(Wm, W0, Wp, Vm, Vp, d.dy, P.gamma, f);
-        z[1] = gate_wave_logit(f, G);
-    }
-    if (lane >= 2 && lane <= 61 && s < d.nx)
-        S.flags[d.cell_off + (long long)t * d.nx + s] =
-            (uint8_t)(fmaxf(z[0], z[1]) >= S.gate_logit_min);
 }
 
 // max over the cells of (|u|+c)/dx + (|v|+c)/dy: SPEED_SPLIT blocks per
@@ -825,12 +842,36 @@ hipError_t launch_speed2d(int eq, const Step2D &S, const DevParams &P, int use_p
     return hipGetLastError();
 }
 
+// Workgroups of the gate kernel: as many as the device holds at once (so no
+// second round of workgroups trails the first), a multiple of 8 (so a
+// workgroup's tiles stay on its XCD), fewer when there are fewer tiles; each
+// walks the running tiles with the grid's stride.
+template <int L>
+static int gate2d_grid(int tiles)
+{
+    static int resident = 0;
+    if (resident == 0) {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gate2d_kernel<L>, 64 * L, 0) !=
+                hipSuccess || per_cu < 1)
+            per_cu = 1;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus < 1)
+            cus = 1;
+        resident = per_cu * cus / 8 * 8;
+        if (resident < 8) resident = 8;
+    }
+    const int g = (tiles + 7) / 8 * 8;
+    return g < resident ? (g < 8 ? 8 : g) : resident;
+}
+
 template <int L>
 static void sweeps2d(int eq, const Step2D &S, const DevParams &P, const int total_tiles[2],
                      hipStream_t st)
 {
     if (eq == EULER && P.weights == W_LEARNED)
-        gate2d_kernel<L><<<total_tiles[0], 64 * L, 0, st>>>(S, P);
+        gate2d_kernel<L><<<gate2d_grid<L>(total_tiles[0]), 64 * L, 0, st>>>(S, P);
     if (eq == EULER && P.weights == W_NONLINEAR) {
         sweep2d_kernel<EULER, 0, L, true><<<total_tiles[0], 64 * L, 0, st>>>(S, P);
         sweep2d_kernel<EULER, 1, L, true><<<total_tiles[1], 64 * L, 0, st>>>(S, P);
