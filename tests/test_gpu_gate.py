@@ -472,3 +472,34 @@ def test_gate_speeds_up_2d_runs(trained):
     print(f"four-quadrant 512^2, 20 steps: gated {t_plain / t_gated:.3f}x plain, "
           f"{flags.mean():.4f} of cells nonlinear")
     assert t_plain / t_gated >= 0.97, (t_plain, t_gated)
+
+
+def test_learned_ragged_batch_matches_instances_run_alone(trained):
+    """The learned gate on a batch whose instances finish at different times
+    (own sizes and end times; the 512^2 instance alone has more tiles than
+    the gate kernel's grid, so its workgroups walk several tiles each): every
+    instance's flags, state and step count equal those of the same instance
+    advanced alone with the same network, bit for bit."""
+    params = trained[2]
+    insts = WL.four_quadrant_batch(count=5, seed=29)
+    sizes = [512, 18, 130, 64, 40]
+    ends = [0.004, 0.05, 0.01, 0.02, 0.03]
+    meshes = [S.Mesh.rect(n, n, 0.0, 1.0, 0.0, 1.0, S.BC_TRANSMISSIVE, S.BC_TRANSMISSIVE)
+              for n in sizes]
+    states = [WL.four_quadrant(n, d.quads) for n, d in zip(sizes, insts)]
+    gp = S.Params.make(eq=S.EULER, weights=S.W_LEARNED, gate_threshold=0.05)
+    b = S.Solver(meshes, gp)
+    b.gate_load(params)
+    for i, st in enumerate(states):
+        b.set_state(i, st)
+    steps = b.advance_to(np.array(ends), raise_nonphysical=False)
+    codes = b.instance_status()
+    assert len(set(steps.tolist())) >= 3           # they do finish at different steps
+    for i, (m, st) in enumerate(zip(meshes, states)):
+        a = S.Solver([m], gp)
+        a.gate_load(params)
+        a.set_state(0, st)
+        k = a.advance_to(ends[i], raise_nonphysical=False)
+        assert k[0] == steps[i] and a.instance_status()[0] == codes[i], i
+        assert np.array_equal(a.get_flags(0), b.get_flags(i)), i
+        assert np.array_equal(a.get_state(0), b.get_state(i)), i
