@@ -849,21 +849,24 @@ hipError_t launch_speed2d(int eq, const Step2D &S, const DevParams &P, int use_p
 template <int L>
 static int gate2d_grid(int tiles)
 {
-    static int resident = 0;
-    if (resident == 0) {
-        int per_cu = 0, dev = 0, cus = 0;
+    constexpr int MAX_DEVICES = 64;
+    static int resident[MAX_DEVICES];          // per device, found on first use
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    int &r = resident[dev >= 0 && dev < MAX_DEVICES ? dev : 0];
+    if (r == 0) {
+        int per_cu = 0, cus = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, gate2d_kernel<L>, 64 * L, 0) !=
                 hipSuccess || per_cu < 1)
             per_cu = 1;
-        (void)hipGetDevice(&dev);
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             cus < 1)
             cus = 1;
-        resident = per_cu * cus / 8 * 8;
-        if (resident < 8) resident = 8;
+        const int g = per_cu * cus / 8 * 8;
+        r = g < 8 ? 8 : g;
     }
     const int g = (tiles + 7) / 8 * 8;
-    return g < resident ? (g < 8 ? 8 : g) : resident;
+    return g < r ? (g < 8 ? 8 : g) : r;
 }
 
 template <int L>
