@@ -291,9 +291,11 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
 #pragma unroll
         for (int n = 0; n <= 4; ++n) {
             double am[M], a0[M], ap[M], bm[M], bp[M];
-            // a compiler barrier: this order's coefficients are read from the
-            // LDS here, not held in registers from an earlier order
-            asm volatile("" ::: "memory");
+            // a compiler barrier at each node's first order: the node reads
+            // the coefficients from the LDS afresh instead of holding them in
+            // registers from the previous node (across the CK series); within
+            // the node the compiler may keep or re-read them
+            if (n == 0) asm volatile("" ::: "memory");
 #pragma unroll
             for (int c = 0; c < M; ++c) {
                 double pw[5], pv[5];
