@@ -569,8 +569,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; a batch would be "
-                                   "sharded by instance across GPUs with no communication "
-                                   "(see the multi-GPU design notes)", "n_gpus": args.gpus}))
+                                   "sharded by instance across GPUs, each GPU advancing its "
+                                   "instances with no communication", "n_gpus": args.gpus}))
         sys.exit(2)
     legs = set(args.legs.split(","))
 

@@ -42,8 +42,8 @@ def test_euler2d_density_wave_matches_paper_table(n, mode):
     """Table ex4.12d (2D Euler density wave, T = 1).  At 10^2 the paper's error
     is 3-5x the oracle's (coarse-grid effects of unprinted details); from
     20^2 on, L1 and L2 agree within 11% (6% at 40^2) and Linf within 25%
-    (8%), converging together (a survey probe of the same reading found 1.2%
-    at 160^2)."""
+    (8%), converging together (an earlier run of the same reading found
+    1.2% at 160^2)."""
     st = WL.density_wave_2d(n)
     cfg = O.Config(eq=O.EULER, weights=mode)
     s, t, steps, bad = O.advance2d(cfg, st, 2.0 / n, 2.0 / n, 0.9, 1.0)
