@@ -387,11 +387,29 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
             }
         }
     }
-    if (!(lane >= 2 && lane <= 61 && s >= 0 && s < ns)) return;
+    // lanes 2..61 own the cells of the tile; in the y-sweep every lane stays
+    // for the wave's reduction of the non-physical flag and the speed
+    const bool own = lane >= 2 && lane <= 61 && s >= 0 && s < ns;
+    if (DIR == 0 && !own) return;
     const int i = DIR == 0 ? s : t, j = DIR == 0 ? t : s;
     const long long plane = (long long)d.nx * d.ny;
     const long long o = (long long)j * d.nx + i;
     const double r = dt / dS, iSS = 1.0 / (d.dx * d.dy);
+    // the y-sweep adds to what the x-sweep wrote: every value it reads is
+    // read before the first store (the stores could alias later reads, so
+    // reads after them would each wait for the previous one's round trip)
+    double Wx[M], Zx[M];
+    if constexpr (DIR == 1) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) { Wx[c] = 1.0; Zx[c] = 0.0; }
+        if (own) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                Wx[c] = dst[c * plane + o];
+                Zx[c] = dst[(3 * M + c) * plane + o];
+            }
+        }
+    }
     double Wn[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
@@ -406,34 +424,44 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
             dst[(M + cc) * plane + o] = dv * iS;
             dst[(3 * M + cc) * plane + o] = zc;
         } else {
-            Wn[cc] = dst[cc * plane + o] - r * (Fu[c] - Fh[c]);
-            dst[cc * plane + o] = Wn[cc];
-            dst[(2 * M + cc) * plane + o] = dv * iS;
-            dst[(3 * M + cc) * plane + o] += zc;
+            Wn[cc] = Wx[cc] - r * (Fu[c] - Fh[c]);
+            if (own) {
+                dst[cc * plane + o] = Wn[cc];
+                dst[(2 * M + cc) * plane + o] = dv * iS;
+                dst[(3 * M + cc) * plane + o] = Zx[cc] + zc;
+            }
         }
     }
     if constexpr (DIR == 1) {
         // non-physical check and the wave speed for the next step's CFL
         bool bad = false;
-#pragma unroll
-        for (int c = 0; c < M; ++c) bad |= !isfinite(Wn[c]);
         double spd = 0.0;
-        if constexpr (EQ == EULER) {
-            const double ir = 1.0 / Wn[0];
-            const double u = Wn[1] * ir, v = Wn[2] * ir;
-            const double p = (P.gamma - 1.0) * (Wn[3] - 0.5 * Wn[0] * (u * u + v * v));
-            bad |= !(Wn[0] > 0.0) || !(p > 0.0);
-            if (!bad) {
-                const double c = sqrt(P.gamma * p * ir);
-                spd = (fabs(u) + c) / d.dx + (fabs(v) + c) / d.dy;
+        if (own) {
+#pragma unroll
+            for (int c = 0; c < M; ++c) bad |= !isfinite(Wn[c]);
+            if constexpr (EQ == EULER) {
+                const double ir = 1.0 / Wn[0];
+                const double u = Wn[1] * ir, v = Wn[2] * ir;
+                const double p = (P.gamma - 1.0) * (Wn[3] - 0.5 * Wn[0] * (u * u + v * v));
+                bad |= !(Wn[0] > 0.0) || !(p > 0.0);
+                if (!bad) {
+                    const double c = sqrt(P.gamma * p * ir);
+                    spd = (fabs(u) + c) / d.dx + (fabs(v) + c) / d.dy;
+                }
+            } else {
+                spd = fabs(P.adv_a) / d.dx + fabs(P.adv_b) / d.dy;
             }
-        } else {
-            spd = fabs(P.adv_a) / d.dx + fabs(P.adv_b) / d.dy;
         }
-        if (bad) atomicOr(&S.bad[inst], 1);
-        // positive doubles order like their bit patterns
-        atomicMax(reinterpret_cast<unsigned long long *>(&S.smax[inst]),
-                  (unsigned long long)__double_as_longlong(spd));
+        // one atomic of each kind per wave (speeds are finite and >= 0, and
+        // such doubles order like their bit patterns)
+        const bool any_bad = __any(bad);
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) spd = fmax(spd, __shfl_xor(spd, m, WAVE));
+        if (lane == 0) {
+            if (any_bad) atomicOr(&S.bad[inst], 1);
+            atomicMax(reinterpret_cast<unsigned long long *>(&S.smax[inst]),
+                      (unsigned long long)__double_as_longlong(spd));
+        }
     }
 }
 
