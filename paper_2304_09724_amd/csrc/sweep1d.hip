@@ -309,6 +309,9 @@ loop1d_kernel(Loop1D Lp, DevParams P)
     // of the averages it produces into one half while the step size of the
     // running step was read from the other
     __shared__ double s_spd[2][NB / WAVE];
+    // per-wave non-physical flags of the averages a sweep produced, buffered
+    // the same way
+    __shared__ int s_bad[2][NB / WAVE];
     __shared__ u32x4 s_gate[EQ == EULER ? GATE_LDS_WORDS : 1];
     const int tid = threadIdx.x;
     if constexpr (LRN) {
@@ -380,10 +383,14 @@ loop1d_kernel(Loop1D Lp, DevParams P)
             double *faces = GUARD ? Lp.faces + 2LL * M * (d.cell_off + i) : nullptr;
             const bool bad = sweep_instance<EQ, NB, LRN, GUARD>(d, A, B, dt, P, Lp.flags, gate_since,
                                                                 s_spd[buf ^ 1], faces);
-            // a full barrier (with workgroup fences) orders the speeds in LDS and
-            // the gate's stored decisions for the next step
+            // one full barrier (with workgroup fences) a step orders the speeds
+            // and flags in LDS and the gate's stored decisions for the next step
+            const bool wave_bad = __any(bad);
+            if (tid % WAVE == 0) s_bad[buf ^ 1][tid / WAVE] = wave_bad;
             __syncthreads();
-            int any_bad = __syncthreads_or(bad);
+            int any_bad = 0;
+#pragma unroll
+            for (int w = 0; w < NB / WAVE; ++w) any_bad |= s_bad[buf ^ 1][w];
             if constexpr (GUARD) {
                 if (any_bad) {
                     const bool still = guard_instance<NB>(d, A, B, dt, P, faces,
