@@ -452,8 +452,8 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
                 spd = fabs(P.adv_a) / d.dx + fabs(P.adv_b) / d.dy;
             }
         }
-        // one atomic of each kind per wave (speeds are finite and >= 0, and
-        // such doubles order like their bit patterns)
+        // one atomic of each kind per wave (speeds are >= 0, and such doubles
+        // order like their bit patterns)
         const bool any_bad = __any(bad);
 #pragma unroll
         for (int m = 32; m > 0; m >>= 1) spd = fmax(spd, __shfl_xor(spd, m, WAVE));
@@ -486,7 +486,8 @@ __device__ __forceinline__ GateLane gate_lane_global(const GateLane *g, int lane
 }
 
 template <int L>
-__global__ void __launch_bounds__(64 * L) gate2d_kernel(Step2D S, DevParams P)
+__global__ void __launch_bounds__(64 * L) __attribute__((amdgpu_waves_per_eu(4)))
+gate2d_kernel(Step2D S, DevParams P)
 {
     constexpr int M = 4;
     // The grid holds as many workgroups as the device runs at once (a
