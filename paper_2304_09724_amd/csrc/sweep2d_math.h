@@ -32,7 +32,11 @@ SHW_HD constexpr int jidx(int a, int n)
 // Output: polynomials in eta = (t - t_j)/dt of the cell's line average of W
 // (PW) and of W_s (PV), per conservative component.
 // --------------------------------------------------------------------------
-template <int M, int EQ, class Re>
+// CW_FULL: whether the componentwise path can meet a cell with nonlinear
+// weights.  Not when the characteristic path is on (Euler, P.charwise) and
+// full is a per-cell choice: a wave with such a cell then takes the
+// characteristic path, and the componentwise weights compile away.
+template <int M, int EQ, bool CW_FULL = true, class Re>
 SHW_HD void stage1(const Re W[3][M], const Re V[3][M], const Re Y[3][M], const Re Z[3][M],
                    double dT, bool full, bool charpath, const DevParams &P, Re PW[M][5],
                    Re PV[M][5])
@@ -100,7 +104,7 @@ SHW_HD void stage1(const Re W[3][M], const Re V[3][M], const Re Y[3][M], const R
     for (int c = 0; c < M; ++c) {
         big_quartic(W[0][c], W[1][c], W[2][c], Re(dT * Y[0][c]), Re(dT * Y[2][c]), PW[c]);
         big_quartic(V[0][c], V[1][c], V[2][c], Re(dT * Z[0][c]), Re(dT * Z[2][c]), PV[c]);
-        if (full) {
+        if (CW_FULL && full) {
             Re w[3];
             nonlinear_weights(PW[c], W[0][c], W[1][c], W[2][c], P, w);
             Re k[3];
@@ -140,7 +144,7 @@ SHW_HD Re taylor_at(const Re c[5], double eta, int n, double scale)
 // times scs[a] (with the node values' own scaling: the kernel's make them
 // Taylor coefficients).
 // --------------------------------------------------------------------------
-template <int M, int EQ, class Re>
+template <int M, int EQ, bool CW_FULL = true, class Re>
 SHW_HD void stage2_order(int n, const Re am[M], const Re a0[M], const Re ap[M], const Re bm[M],
                          const Re bp[M], const CharX<Re> &E, double dS,
                          const double scs[5], bool full, bool charpath, const DevParams &P,
@@ -196,7 +200,7 @@ SHW_HD void stage2_order(int n, const Re am[M], const Re a0[M], const Re ap[M], 
 #pragma unroll
         for (int c = 0; c < M; ++c) {
             big_quartic(am[c], a0[c], ap[c], Re(dS * bm[c]), Re(dS * bp[c]), cq[c]);
-            if (full) {
+            if (CW_FULL && full) {
                 if (n == 0) {
                     Re wn[3];
                     nonlinear_weights(cq[c], am[c], a0[c], ap[c], P, wn);
