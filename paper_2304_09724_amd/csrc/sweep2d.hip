@@ -175,13 +175,13 @@ __device__ __forceinline__ long long yface_rec(const Inst2D &d, int q, int i, in
 }
 
 // FULL: every cell takes the nonlinear weights (the paper's scheme): the
-// per-cell choice and its branches compile away.  CW_FULL: the
-// componentwise path can meet a nonlinear-weight cell (false only for a
-// per-cell choice with the characteristic path on: see stage1).
-template <int EQ, int DIR, int L, bool FULL, bool CW_FULL>
+// per-cell choice and its branches compile away.  CHAR (Euler): launched
+// only with the characteristic path on (P.charwise), which compiles away
+// the componentwise path's weights, and with FULL the whole componentwise
+// path (see stage1).
+template <int EQ, int DIR, int L, bool FULL, bool CHAR>
 __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
 {
-    static_assert(CW_FULL || (EQ == EULER && !FULL), "componentwise weights needed");
     constexpr int NB = 64 * L;
     constexpr int M = NComp<EQ, 2>::M;
     const int bid = xcd_running_tile(blockIdx.x, S.act_n[1 + DIR]);
@@ -235,7 +235,7 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
         // the nonlinear weights
         charpath = FULL || __any(full);
         if (live) {
-            stage1<M, EQ, CW_FULL>(W, V, Y, Z, dT, full, charpath, P, PW, PV);
+            stage1<M, EQ, CHAR, FULL>(W, V, Y, Z, dT, full, charpath, P, PW, PV);
 #pragma unroll
             for (int c = 0; c < M; ++c) Wc[c] = W[1][c];
         } else {
@@ -320,8 +320,8 @@ __global__ void __launch_bounds__(64 * L) sweep2d_kernel(Step2D S, DevParams P)
             // polynomials and a unit state) work on finite data too, and
             // leaving them out would cost a branch that clears their jets
             double lo[5][M], hi[5][M];
-            stage2_order<M, EQ, CW_FULL>(n, am, a0, ap, bm, bp, Em, dS, scs, full, charpath, P, w,
-                                         lo, hi);
+            stage2_order<M, EQ, CHAR, FULL>(n, am, a0, ap, bm, bp, Em, dS, scs, full, charpath, P,
+                                            w, lo, hi);
 #pragma unroll
             for (int a = 0; a + n <= 4; ++a) {
                 double JL[M];
@@ -910,18 +910,22 @@ static void sweeps2d(int eq, const Step2D &S, const DevParams &P, const int tota
 {
     if (eq == EULER && P.weights == W_LEARNED)
         gate2d_kernel<L><<<gate2d_grid<L>(total_tiles[0]), 64 * L, 0, st>>>(S, P);
-    if (eq == EULER && P.weights == W_NONLINEAR) {
+    const bool full = P.weights == W_NONLINEAR;
+    if (eq == EULER && full && P.charwise) {
         sweep2d_kernel<EULER, 0, L, true, true><<<total_tiles[0], 64 * L, 0, st>>>(S, P);
         sweep2d_kernel<EULER, 1, L, true, true><<<total_tiles[1], 64 * L, 0, st>>>(S, P);
+    } else if (eq == EULER && full) {
+        sweep2d_kernel<EULER, 0, L, true, false><<<total_tiles[0], 64 * L, 0, st>>>(S, P);
+        sweep2d_kernel<EULER, 1, L, true, false><<<total_tiles[1], 64 * L, 0, st>>>(S, P);
     } else if (eq == EULER && P.charwise) {
-        sweep2d_kernel<EULER, 0, L, false, false><<<total_tiles[0], 64 * L, 0, st>>>(S, P);
-        sweep2d_kernel<EULER, 1, L, false, false><<<total_tiles[1], 64 * L, 0, st>>>(S, P);
-    } else if (eq == EULER) {
         sweep2d_kernel<EULER, 0, L, false, true><<<total_tiles[0], 64 * L, 0, st>>>(S, P);
         sweep2d_kernel<EULER, 1, L, false, true><<<total_tiles[1], 64 * L, 0, st>>>(S, P);
+    } else if (eq == EULER) {
+        sweep2d_kernel<EULER, 0, L, false, false><<<total_tiles[0], 64 * L, 0, st>>>(S, P);
+        sweep2d_kernel<EULER, 1, L, false, false><<<total_tiles[1], 64 * L, 0, st>>>(S, P);
     } else {
-        sweep2d_kernel<ADV, 0, L, false, true><<<total_tiles[0], 64 * L, 0, st>>>(S, P);
-        sweep2d_kernel<ADV, 1, L, false, true><<<total_tiles[1], 64 * L, 0, st>>>(S, P);
+        sweep2d_kernel<ADV, 0, L, false, false><<<total_tiles[0], 64 * L, 0, st>>>(S, P);
+        sweep2d_kernel<ADV, 1, L, false, false><<<total_tiles[1], 64 * L, 0, st>>>(S, P);
     }
 }
 

@@ -32,15 +32,20 @@ SHW_HD constexpr int jidx(int a, int n)
 // Output: polynomials in eta = (t - t_j)/dt of the cell's line average of W
 // (PW) and of W_s (PV), per conservative component.
 // --------------------------------------------------------------------------
-// CW_FULL: whether the componentwise path can meet a cell with nonlinear
-// weights.  Not when the characteristic path is on (Euler, P.charwise) and
-// full is a per-cell choice: a wave with such a cell then takes the
-// characteristic path, and the componentwise weights compile away.
-template <int M, int EQ, bool CW_FULL = true, class Re>
+// Promises a caller may make at compile time (both false: nothing
+// promised).  CHAR (Euler): P.charwise is on; a wave with a nonlinear-weight
+// cell then takes the characteristic path, so the componentwise path never
+// meets such a cell and its weights compile away.  FULL with CHAR: every
+// cell takes the nonlinear weights (charpath holds for every wave), and the
+// componentwise path compiles away.  The run-time tests stay as they are
+// (their outcome is then known; keeping them left the compiler's register
+// allocation of the sweeps better than folding them).
+template <int M, int EQ, bool CHAR = false, bool FULL = false, class Re>
 SHW_HD void stage1(const Re W[3][M], const Re V[3][M], const Re Y[3][M], const Re Z[3][M],
                    double dT, bool full, bool charpath, const DevParams &P, Re PW[M][5],
                    Re PV[M][5])
 {
+    static_assert(!CHAR || EQ == EULER, "characteristic path: Euler only");
     if constexpr (EQ == EULER) {
         if (charpath && P.charwise) {
             // The transverse Jacobian's fields (those of euler_eigen<2, 1>)
@@ -100,17 +105,19 @@ SHW_HD void stage1(const Re W[3][M], const Re V[3][M], const Re Y[3][M], const R
             return;
         }
     }
+    if constexpr (!(CHAR && FULL)) {
 #pragma unroll
-    for (int c = 0; c < M; ++c) {
-        big_quartic(W[0][c], W[1][c], W[2][c], Re(dT * Y[0][c]), Re(dT * Y[2][c]), PW[c]);
-        big_quartic(V[0][c], V[1][c], V[2][c], Re(dT * Z[0][c]), Re(dT * Z[2][c]), PV[c]);
-        if (CW_FULL && full) {
-            Re w[3];
-            nonlinear_weights(PW[c], W[0][c], W[1][c], W[2][c], P, w);
-            Re k[3];
-            combine_factors(w, P, k);
-            combine(PW[c], W[0][c], W[1][c], W[2][c], k);
-            combine(PV[c], V[0][c], V[1][c], V[2][c], k);
+        for (int c = 0; c < M; ++c) {
+            big_quartic(W[0][c], W[1][c], W[2][c], Re(dT * Y[0][c]), Re(dT * Y[2][c]), PW[c]);
+            big_quartic(V[0][c], V[1][c], V[2][c], Re(dT * Z[0][c]), Re(dT * Z[2][c]), PV[c]);
+            if (!CHAR && full) {
+                Re w[3];
+                nonlinear_weights(PW[c], W[0][c], W[1][c], W[2][c], P, w);
+                Re k[3];
+                combine_factors(w, P, k);
+                combine(PW[c], W[0][c], W[1][c], W[2][c], k);
+                combine(PV[c], V[0][c], V[1][c], V[2][c], k);
+            }
         }
     }
 }
@@ -144,12 +151,13 @@ SHW_HD Re taylor_at(const Re c[5], double eta, int n, double scale)
 // times scs[a] (with the node values' own scaling: the kernel's make them
 // Taylor coefficients).
 // --------------------------------------------------------------------------
-template <int M, int EQ, bool CW_FULL = true, class Re>
+template <int M, int EQ, bool CHAR = false, bool FULL = false, class Re>
 SHW_HD void stage2_order(int n, const Re am[M], const Re a0[M], const Re ap[M], const Re bm[M],
                          const Re bp[M], const CharX<Re> &E, double dS,
                          const double scs[5], bool full, bool charpath, const DevParams &P,
                          Re w[M][3], Re lo[5][M], Re hi[5][M])
 {
+    static_assert(!CHAR || EQ == EULER, "characteristic path: Euler only");
     const bool proj = EQ == EULER && charpath && P.charwise;
     Re cq[M][5];
     bool done = false;
@@ -196,17 +204,19 @@ SHW_HD void stage2_order(int n, const Re am[M], const Re a0[M], const Re ap[M], 
             done = true;
         }
     }
-    if (!done) {
+    if constexpr (!(CHAR && FULL)) {
+        if (!done) {
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-            big_quartic(am[c], a0[c], ap[c], Re(dS * bm[c]), Re(dS * bp[c]), cq[c]);
-            if (CW_FULL && full) {
-                if (n == 0) {
-                    Re wn[3];
-                    nonlinear_weights(cq[c], am[c], a0[c], ap[c], P, wn);
-                    combine_factors(wn, P, w[c]);
+            for (int c = 0; c < M; ++c) {
+                big_quartic(am[c], a0[c], ap[c], Re(dS * bm[c]), Re(dS * bp[c]), cq[c]);
+                if (!CHAR && full) {
+                    if (n == 0) {
+                        Re wn[3];
+                        nonlinear_weights(cq[c], am[c], a0[c], ap[c], P, wn);
+                        combine_factors(wn, P, w[c]);
+                    }
+                    combine(cq[c], am[c], a0[c], ap[c], w[c]);
                 }
-                combine(cq[c], am[c], a0[c], ap[c], w[c]);
             }
         }
     }
