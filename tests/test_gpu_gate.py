@@ -426,13 +426,15 @@ def test_gate_speeds_up_2d_runs(trained):
     smooth 2D density wave (512^2, 20 steps; every cell passed as smooth)
     the learned gate runs at least 2% faster than the plain scheme (1.04x
     measured); on a four-quadrant problem (512^2, 20 steps), whose
-    discontinuities cross most 60-cell lines, at most 3% slower (1.01x
+    discontinuities cross most 60-cell lines, at most 3% slower (1.02x
     measured); best of three each.  The saving is capped by what the weights
     cost: the Lax-Wendroff series, the seeds and the fluxes, most of a 2D
-    cell-update, do not depend on them, and the gate pass costs about 5% of
+    cell-update, do not depend on them, and the gate pass costs about 3% of
     a plain step.  The four-quadrant gain went from 1.25x through 1.12x and
     1.08x to 1.01x as the plain path got cheaper, the last step being the
-    plain scheme's own compiled instance with no per-cell weight choice."""
+    plain scheme's own compiled instance with no per-cell weight choice,
+    and back to 1.02x when the gated instance lost the componentwise
+    path's weight branch."""
     import time
     params = trained[2]
     n = 512
