@@ -102,8 +102,12 @@ def test_mixed_boundaries():
 
 
 @pytest.mark.parametrize("weights,charwise", [(S.W_LINEAR, True), (S.W_NONLINEAR, False),
-                                              (S.W_GATED, True)])
+                                              (S.W_GATED, True), (S.W_GATED, False)])
 def test_weight_modes(weights, charwise):
+    """Each compiled instance of the sweeps against the oracle on a
+    four-quadrant problem, three steps: the paper's scheme with the
+    characteristic path off, linear weights, and per-cell flags (40 % set)
+    with the characteristic path on and off."""
     n = 24
     quads = [(1.1, 0.0, 0.0, 1.1), (0.5065, 0.8939, 0.0, 0.35), (1.1, 0.8939, 0.8939, 1.1),
              (0.5065, 0.0, 0.8939, 0.35)]
